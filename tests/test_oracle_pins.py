@@ -1,0 +1,441 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: an
+independent Philox implementation (rocRAND), closed forms of the Laplace
+transform, exact rational arithmetic, algebraic invariants of the moves,
+brute-force minima of tiny problems, and the defining formulas of the
+branching multipliers.
+"""
+import math
+import os
+import shutil
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1609_07936_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("hipcc / rocRAND headers not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "rr_ref")
+    subprocess.run([hipcc, "-O1", "-o", exe, os.path.join(HERE, "rocrand_philox_ref.cpp")], check=True,
+                   cwd="/tmp", timeout=600)
+    return exe
+
+
+def test_philox_matches_rocrand(rocrand_ref):
+    rng = np.random.default_rng(123)
+    # the helper passes 4 * (c1:c0) as a 64-bit offset, so c1 stays below 2^30
+    cases = [(0, 0, 0, 0, 0, 0), (0xFFFFFFFF, 0x3FFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF),
+             (1, 2, 3, 4, 5, 6), (63, 1999, 63, 0, 1, 0), (0, 0, 0, 0x42524E43, 2, 0)]
+    for _ in range(200):
+        c = [int(v) for v in rng.integers(0, 2 ** 32, 6, dtype=np.uint64)]
+        c[1] >>= 2
+        cases.append(tuple(c))
+    inp = "\n".join(" ".join(str(v) for v in c) for c in cases) + "\n"
+    out = subprocess.run([rocrand_ref], input=inp, capture_output=True, text=True, check=True, timeout=60).stdout
+    ref = [tuple(int(v) for v in line.split()) for line in out.strip().splitlines()]
+    assert len(ref) == len(cases)
+    for c, r in zip(cases, ref):
+        got = tuple(int(v) for v in O.philox4x32_10(c[:4], c[4:]))
+        assert got == r, (c, got, r)
+
+
+def test_philox_words_look_uniform():
+    key = (7, 0)
+    words = np.array([O.philox4x32_10((q, 0, 0, 0), key) for q in range(4000)]).ravel()
+    u = O.u01(words)
+    assert abs(u.mean() - 0.5) < 0.01 and abs(u.var() - 1.0 / 12.0) < 0.005
+    hist = np.bincount((words.astype(np.uint64) * 64) >> 32, minlength=64)
+    chi = np.sum((hist - hist.mean()) ** 2 / hist.mean())
+    assert chi < 120  # 63 dof
+
+
+# --------------------------------------------------------------------------
+# Kernel table, Sec. 2.1
+# --------------------------------------------------------------------------
+def _lorentz_transform_closed(w0, g, W_, tau):
+    """(1/2pi) int_0^W L(omega; w0, g) e^{-omega tau} d omega via the complex E1."""
+    from scipy.special import exp1
+    z = complex(w0, g)
+    tau = np.asarray(tau, dtype=np.float64)
+    val = np.exp(-z * tau) * (exp1(-z * tau) - exp1((W_ - z) * tau))
+    return np.imag(val) / np.pi / (2.0 * np.pi)
+
+
+def test_point_mode_is_midpoint_rule_of_transform():
+    """POINT mode samples each bin at its centre: for a smooth spectrum the
+    model transform converges to Eq. (transform) at second order in d_omega."""
+    tau = np.linspace(0.05, 2.0, 9)
+    exact = _lorentz_transform_closed(2.0, 0.7, 8.0, tau)
+    errs = []
+    for n in (200, 400, 800):
+        om = W.bin_centres(8.0, n)
+        K = O.kernel_table(O.POINT, om, tau)
+        a = W.lorentzian(om, 2.0, 0.7)
+        errs.append(np.max(np.abs(O.forward(K, a) - exact) / exact))
+    assert errs[-1] < 1e-5
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_bin_exact_box_telescopes():
+    """A box of height h on bins [ja, jb) transforms to h (e^{-w_a t} - e^{-w_b t}) / (2 pi t)."""
+    n, wmax = 40, 6.0
+    om = W.bin_centres(wmax, n)
+    dw = wmax / n
+    tau = np.array([0.0, 0.01, 0.3, 1.0, 2.5])
+    K = O.kernel_table(O.BIN_EXACT, om, tau)
+    a = np.zeros(n)
+    ja, jb, h = 7, 23, 1.7
+    a[ja:jb] = h
+    F = O.forward(K, a)
+    wa, wb = ja * dw, jb * dw
+    ref = np.where(tau > 0, h * (np.exp(-wa * tau) - np.exp(-wb * tau)) / (2 * np.pi * np.where(tau > 0, tau, 1)),
+                   h * (wb - wa) / (2 * np.pi))
+    np.testing.assert_allclose(F, ref, rtol=1e-13)
+
+
+def test_bin_exact_matches_paper_power_form():
+    """Eq. (efficient-correlation-model) with Eq. (c-coefficients): on
+    tau_i = i d_tau, F(tau_i) = c_i sum_j a_j (e^{-d_omega d_tau})^{ij}."""
+    n, wmax, nt, dt = 30, 5.0, 12, 0.17
+    om = W.bin_centres(wmax, n)
+    dw = wmax / n
+    tau = dt * np.arange(nt)
+    K = O.kernel_table(O.BIN_EXACT, om, tau)
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0.0, 1.0, n)
+    F = O.forward(K, a)
+    q = math.exp(-dw * dt)
+    power = []
+    for i in range(nt):
+        c = dw / (2 * math.pi) if i == 0 else (1 - math.exp(-i * dw * dt)) / (2 * math.pi * i * dt)
+        power.append(c * sum(a[j] * q ** (i * j) for j in range(n)))
+    np.testing.assert_allclose(F, power, rtol=1e-13)
+
+
+def test_forward_is_linear_and_chi2_unweighted_default():
+    om = W.bin_centres(4.0, 10)
+    tau = np.linspace(0.1, 1, 5)
+    K = O.kernel_table(O.POINT, om, tau)
+    rng = np.random.default_rng(0)
+    a, b = rng.uniform(size=10), rng.uniform(size=10)
+    np.testing.assert_allclose(O.forward(K, a + b), O.forward(K, a) + O.forward(K, b), rtol=1e-14)
+    F, Ft = O.forward(K, a), O.forward(K, b)
+    assert O.chi2(F, F, np.ones(5)) == 0.0
+    assert math.isclose(O.chi2(F, Ft, np.ones(5)), float(np.sum((F - Ft) ** 2)), rel_tol=1e-14)
+    w = rng.uniform(1, 2, 5)
+    assert math.isclose(O.chi2(F, Ft, w), float(np.sum(w * (F - Ft) ** 2)), rel_tol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Sum rules, initial spectrum, renormalisation (Sec. 2.2)
+# --------------------------------------------------------------------------
+def test_init_spectrum_meets_sum_rules():
+    om = W.bin_centres(10.0, 64)
+    for mu in (0.3, 2.5, 5.0, 7.7, 9.8):
+        A = 6.4
+        a, lam = O.init_spectrum(om, A, A * mu)
+        assert np.all(a > 0)
+        assert abs(a.sum() - A) <= 4e-15 * A
+        assert abs((a * om).sum() - A * mu) <= 4e-15 * A * mu
+        assert (lam > 0) == (mu < 5.0) or mu == 5.0
+    a, lam = O.init_spectrum(om, 1.0, 5.0)  # window centre: uniform, lambda = 0
+    assert lam == 0.0
+    np.testing.assert_allclose(a, np.full(64, 1.0 / 64), rtol=1e-14)
+    with pytest.raises(ValueError):
+        O.init_spectrum(om, 1.0, 0.01)
+    with pytest.raises(ValueError):
+        O.init_spectrum(om, 1.0, 10.5)
+
+
+def test_renormalize_restores_both_sums():
+    om = W.bin_centres(10.0, 64)
+    rng = np.random.default_rng(2)
+    a = rng.uniform(0.1, 1.0, 64)
+    A, B = a.sum(), (a * om).sum()
+    pert = a * (1 + 1e-9 * rng.standard_normal(64))
+    b = O.renormalize(pert, om, A, B)
+    assert abs(b.sum() - A) <= 4e-16 * 64 * A
+    assert abs((b * om).sum() - B) <= 4e-16 * 64 * B
+    assert np.max(np.abs(b / a - 1)) < 1e-8
+
+
+def test_move_conserves_sums_and_is_reversible():
+    om = W.bin_centres(10.0, 64)
+    rng = np.random.default_rng(9)
+    a = rng.uniform(0.1, 1.0, 64)
+    A, B = float(a.sum()), float((a * om).sum())
+    for _ in range(200):
+        p, s = rng.choice(64, 2, replace=False)
+        r = float(rng.uniform(0.9, 1.1))
+        dp, ds = O.move_deltas(om, A, B, p, s, r)
+        a2 = r * a
+        a2[p] += dp
+        a2[s] += ds
+        # Eqs. (update-scheme) with (update-delta): both sums unchanged
+        assert abs(a2.sum() - A) <= 1e-14 * A
+        assert abs((a2 * om).sum() - B) <= 1e-14 * B
+        # the inverse move is the same kind of move with r' = 1/r
+        ip, is_ = O.move_deltas(om, A, B, p, s, 1.0 / r)
+        assert math.isclose(ip, -dp / r, rel_tol=1e-12, abs_tol=1e-300)
+        assert math.isclose(is_, -ds / r, rel_tol=1e-12, abs_tol=1e-300)
+        a3 = (1.0 / r) * a2
+        a3[p] += ip
+        a3[s] += is_
+        np.testing.assert_allclose(a3, a, rtol=1e-12, atol=1e-14)
+    assert O.move_deltas(om, A, B, 5, 5, 0.95) == (0.0, 0.0)
+
+
+def _c1_problem(noise_free=False, sigma=True):
+    wl = W.config1()
+    Ft = wl.F_true if noise_free else wl.Ft
+    return wl, O.Problem(wl.omega, wl.tau, Ft, wl.sigma if sigma else None, wl.m0, wl.m1)
+
+
+@pytest.mark.slow
+def test_sum_rule_drift_after_a_million_moves():
+    wl, prob = _c1_problem()
+    S = 36000
+    sched = O.Schedule(np.full(S, 10.0), branch_every=10 ** 6, resync_every=10 ** 6)
+    an = O.Anneal(prob, sched, 4, 3)
+    out = an.run(0, S)
+    assert out["accepted"] / 4 > 1e6
+    for l in range(4):
+        a = an.a[l]
+        assert np.all(a >= 0)
+        assert abs(a.sum() - prob.A) <= 1e-12 * prob.A
+        assert abs((a * prob.omega).sum() - prob.B) <= 1e-12 * prob.B
+
+
+def test_incremental_F_and_chi2_match_recomputation():
+    wl, prob = _c1_problem()
+    S = 300
+    sched = O.Schedule(W.geometric_schedule(1e2, 1e-2, S), branch_every=10 ** 6, resync_every=10 ** 6)
+    an = O.Anneal(prob, sched, 8, 5)
+    out = an.run(0, S)
+    assert out["accepted"] > 10000
+    for l in range(8):
+        Ffull = O.forward(prob.K, an.a[l])
+        # drift of F: a few ulp per accepted move, relative to |F|
+        assert np.max(np.abs(an.F[l] - Ffull) / np.abs(Ffull)) < 1e-12
+        c_full = O.chi2(Ffull, prob.Ft, prob.w)
+        # chi^2 sensitivity: d chi^2 = 2 sum w R dF with |dF| <= 1e-12 |F|
+        bound = 2 * np.sum(prob.w * np.abs(an.F[l] - prob.Ft) * 1e-12 * np.abs(Ffull)) + 1e-12 * c_full
+        assert abs(an.chi2[l] - c_full) <= bound
+
+
+def test_first_proposal_dchi2_exact_rational():
+    """The traced dchi^2 of each walker's first proposal (state known exactly)
+    against chi^2(F + dF) - chi^2(F) in exact rational arithmetic, with the
+    move rebuilt from the Philox words and the documented maps."""
+    wl, prob = _c1_problem()
+    sched = O.Schedule(W.geometric_schedule(1e2, 1e-3, 2000))
+    an = O.Anneal(prob, sched, 16, wl.seed)
+    F0 = an.F[0].copy()
+    out = an.run(0, 1, trace=(0, 1))
+    No = prob.omega.size
+    key = (wl.seed & 0xFFFFFFFF, wl.seed >> 32)
+    for l in range(16):
+        x = O.philox4x32_10((0, 0, l, 0), key)
+        p, s = (int(x[0]) * No) >> 32, (int(x[1]) * No) >> 32
+        ur = float(O.u01(x[2]))
+        r = 1.0 - 1.0 * 0.1 * (2.0 * ur - 1.0)
+        dp, ds = O.move_deltas(prob.omega, prob.A, prob.B, p, s, r)
+        Fr = [Fraction(v) for v in F0]
+        dF = [Fraction(r - 1.0) * Fraction(F0[i]) + Fraction(dp) * Fraction(prob.K[p, i]) +
+              Fraction(ds) * Fraction(prob.K[s, i]) for i in range(F0.size)]
+        wts = [Fraction(v) for v in prob.w]
+        Ftf = [Fraction(v) for v in prob.Ft]
+        c_old = sum(w_ * (f - t) ** 2 for w_, f, t in zip(wts, Fr, Ftf))
+        c_new = sum(w_ * (f + d - t) ** 2 for w_, f, d, t in zip(wts, Fr, dF, Ftf))
+        exact = float(c_new - c_old)
+        got = out["dchi2"][l, 0, 0]
+        M = out["cond"][l, 0, 0]
+        assert abs(got - exact) <= 1e-13 * M, (l, got, exact, M)
+
+
+def test_zero_temperature_never_raises_chi2_and_infinite_accepts_all_admissible():
+    wl, prob = _c1_problem()
+    S = 20
+    for T, check in ((1e-300, "cold"), (1e300, "hot")):
+        sched = O.Schedule(np.full(S, T), branch_every=10 ** 6, resync_every=10 ** 6)
+        an = O.Anneal(prob, sched, 8, 21)
+        out = an.run(0, S, trace=(0, S))
+        acc = (out["accept"] & 1).astype(bool)
+        ok = (out["accept"] & 2).astype(bool)
+        if check == "cold":
+            assert np.all(out["dchi2"][acc] <= 0.0)
+            assert acc.sum() > 0
+        else:
+            assert np.array_equal(acc, ok)
+            assert (~ok).sum() > 0  # the positivity cut is exercised
+
+
+# --------------------------------------------------------------------------
+# Brute force on tiny problems and noise-free recovery
+# --------------------------------------------------------------------------
+def _qp_min(K, Ft, w, om, A, B):
+    """min sum w (K^T a - Ft)^2 s.t. sum a = A, sum a om = B, a >= 0, by
+    enumerating the faces (sets of coefficients held at zero)."""
+    import itertools
+    n = om.size
+    G = K.T * np.sqrt(w)[:, None]
+    y = Ft * np.sqrt(w)
+    best = (np.inf, None)
+    for nz in range(0, n - 1):
+        for zero in itertools.combinations(range(n), nz):
+            free = [j for j in range(n) if j not in zero]
+            Gf = G[:, free]
+            C = np.vstack([np.ones(len(free)), om[free]])
+            d = np.array([A, B])
+            kkt = np.block([[2 * Gf.T @ Gf, C.T], [C, np.zeros((2, 2))]])
+            rhs = np.concatenate([2 * Gf.T @ y, d])
+            try:
+                sol = np.linalg.solve(kkt, rhs)
+            except np.linalg.LinAlgError:
+                continue
+            af = sol[:len(free)]
+            if np.any(af < -1e-12 * A):
+                continue
+            a = np.zeros(n)
+            a[free] = af
+            val = float(np.sum((G @ a - y) ** 2))
+            if val < best[0]:
+                best = (val, a)
+    return best
+
+
+@pytest.mark.parametrize("n_omega", [3, 4])
+def test_anneal_reaches_brute_force_minimum(n_omega):
+    om = W.bin_centres(3.0, n_omega)
+    tau = np.linspace(0.1, 2.0, 12)
+    K = O.kernel_table(O.POINT, om, tau)
+    rng = np.random.default_rng(40 + n_omega)
+    a_true = rng.uniform(0.2, 1.0, n_omega)
+    Ft = (K.T @ a_true) * (1 + 1e-3 * np.sin(np.arange(12.0)))
+    dw = om[1] - om[0]
+    prob = O.Problem(om, tau, Ft, None, a_true.sum() * dw, (a_true * om).sum() * dw)
+    cmin, amin = _qp_min(K, Ft, np.ones(12), om, prob.A, prob.B)
+    S = 4000
+    an = O.Anneal(prob, O.Schedule(W.geometric_schedule(1.0, 1e-16, S)), 16, 7)
+    an.run(0, S)
+    best = float(an.chi2.min())
+    # never below the constrained minimum (up to rounding), and close to it
+    assert best >= cmin * (1 - 1e-9)
+    assert best <= cmin * (1 + 1e-6), (best, cmin)
+
+
+def test_noise_free_tiny_problem_recovers_near_zero_chi2():
+    om = W.bin_centres(4.0, 8)
+    tau = W.uniform_tau(0.05, 2.0, 16)
+    K = O.kernel_table(O.POINT, om, tau)
+    a_true = np.random.default_rng(3).uniform(0.2, 1.0, 8)
+    Ft = K.T @ a_true
+    dw = om[1] - om[0]
+    prob = O.Problem(om, tau, Ft, None, a_true.sum() * dw, (a_true * om).sum() * dw)
+    S = 4000
+    an = O.Anneal(prob, O.Schedule(W.geometric_schedule(1.0, 1e-16, S)), 32, 11)
+    an.run(0, S)
+    assert an.chi2.min() / an.chi2_unit < 1e-7
+
+
+# --------------------------------------------------------------------------
+# Branching, Sec. 2.5
+# --------------------------------------------------------------------------
+def test_branch_multipliers_follow_the_paper_formula():
+    rng = np.random.default_rng(17)
+    for n in (16, 64, 257, 1000):
+        chi2 = np.exp(rng.normal(0, 1.0, n))
+        xi = rng.uniform(0, 1, n)
+        res = O.branch_solve(chi2, xi, 0.25)
+        assert res["status"] == 0
+        m = res["m"]
+        assert m.sum() == n
+        # m = floor(w + xi) with w = exp[-(chi^2 - P_r) Delta]
+        w = np.exp(-(chi2 - res["pr"]) * res["delta"])
+        np.testing.assert_array_equal(m, np.floor(w + xi).astype(np.int32))
+        zt = int(math.floor(0.25 * n + 0.5))
+        assert res["z"] == int((m == 0).sum()) and res["z"] >= zt
+        assert res["z"] <= zt + 2
+        # P_r lies between the n-th and (n+1)-th smallest thresholds
+        ks = np.arange(1, n + 2)
+        th = np.sort((chi2[:, None] + np.log(ks[None, :] - xi[:, None]) / res["delta"]).ravel())
+        assert th[n - 1] <= res["pr"] < th[n]
+
+
+def test_branch_multiplier_has_mean_w():
+    """E[floor(w + xi)] = w for xi uniform on (0, 1) (Sec. 2.5)."""
+    rng = np.random.default_rng(1)
+    for w in (0.0, 0.3, 1.0, 1.7, 4.25):
+        xi = rng.uniform(0, 1, 200000)
+        assert abs(np.floor(w + xi).mean() - w) < 5e-3
+
+
+def test_branch_degenerate_cases_are_skipped():
+    res = O.branch_solve(np.full(32, 3.0), np.linspace(0.01, 0.99, 32), 0.25)
+    assert res["status"] == 1 and np.all(res["m"] == 1)
+    res = O.branch_solve(np.linspace(1, 2, 3), np.array([0.1, 0.5, 0.9]), 0.1)
+    assert res["status"] == 1  # round(0.3) = 0 walkers to branch
+
+
+def test_pairing_and_imprint_invariants():
+    m = np.array([0, 3, 1, 0, 2, 0, 1, 0, 2], dtype=np.int32)
+    tg, dn = O.branch_pairs(m)
+    assert tg.tolist() == [0, 3, 5, 7]
+    assert dn.tolist() == [1, 1, 4, 8]
+    wl, prob = _c1_problem()
+    for t in (1.0, 0.1):
+        sched = O.Schedule(W.geometric_schedule(1e2, 1e-3, 200), imprint_t=t)
+        an = O.Anneal(prob, sched, 32, 4)
+        an.run(0, 99)
+        an.run(99, 100)  # resync + branching event 0 after sweep 99
+        assert an.ev_status[0] == 0
+        before = an.a.copy()
+        m = an.ev_m[0]
+        tg, dn = O.branch_pairs(m)
+        assert len(tg) == an.ev_z[0] >= 8
+        # after the event the targets hold t a_donor + (1 - t) a_target; the
+        # donors are untouched.  Rebuild from a fresh copy run to the same point.
+        an2 = O.Anneal(prob, sched, 32, 4)
+        an2.run(0, 99)
+        an2.args.branch_every = 10 ** 6
+        an2.run(99, 100)
+        pre = an2.a  # resynced state, no branching
+        for l1, l2 in zip(tg, dn):
+            expect = t * pre[l2] + (1.0 - t) * pre[l1]
+            if t == 1.0:
+                assert np.array_equal(before[l1], pre[l2])  # exact copy
+            np.testing.assert_allclose(before[l1], expect, rtol=1e-15, atol=0)
+            assert abs(before[l1].sum() - prob.A) <= 1e-13 * prob.A
+            assert abs((before[l1] * prob.omega).sum() - prob.B) <= 1e-13 * prob.B
+            np.testing.assert_allclose(an.F[l1], O.forward(prob.K, before[l1]), rtol=1e-15)
+        keep = np.setdiff1d(np.arange(32), tg)
+        assert np.array_equal(before[keep], pre[keep])
+
+
+# --------------------------------------------------------------------------
+# Outputs (Eq. residue-average)
+# --------------------------------------------------------------------------
+def test_outputs():
+    wl, prob = _c1_problem()
+    an = O.Anneal(prob, O.Schedule(W.geometric_schedule(1e2, 1e-3, 200)), 16, 2)
+    an.run(0, 200)
+    np.testing.assert_allclose(an.mean_spectrum(), an.a.mean(axis=0), rtol=1e-14)
+    lo, hi = np.log10(an.chi2.min()), np.log10(an.chi2.max())
+    h = O.chi2_hist(an.chi2, 64, lo, hi)
+    assert h.sum() == 16 and h[0] >= 1 and h[-1] >= 1
+    h2 = O.chi2_hist(np.array([1.0, 10.0, 100.0, 1000.0]), 3, 0.0, 3.0)
+    assert h2.tolist() == [1, 1, 2]
