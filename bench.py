@@ -1,0 +1,148 @@
+"""Benchmark: walker proposals per second of the annealing hot path.
+
+One step = one block of the anneal on one GPU: 100 sweeps of every walker
+(each sweep N_omega proposals: Philox draws, sum-rule move, incremental
+residual loop over all tau, reduction, Metropolis accept), the exact resync
+of every walker, and one imprinted-branching event (solve, imprint,
+recompute of the targets).  The default workload is the production-scale
+FP64 configuration: 512 bins on [0, 20], 128 times on [0.02, 3], 16384
+walkers, 20000 sweeps (200 steps), double-Lorentzian synthetic data with
+1e-5 relative noise.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the driver contract): the metric, the roofline
+of the sweep kernel from HIP events on its launch stream, and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector
+SWEEPS_PER_STEP = 100
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed blocks of 100 sweeps (200 = the whole anneal)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c2"])
+    ap.add_argument("--cpu-sample-walkers", type=int, default=1024)
+    ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, T, n_walkers, n_sweeps) -> dict:
+    import oracle as O
+    op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    stride = max(1, wl.n_walkers // n_walkers)
+    ids = np.arange(0, wl.n_walkers, stride)[:n_walkers]
+    an = O.Anneal(op, O.Schedule(T), wl.n_walkers, wl.seed, walker_ids=ids)
+    t0 = time.perf_counter()
+    out = an.run(0, n_sweeps)
+    dt = time.perf_counter() - t0
+    return {"value": out["proposals"] / dt, "unit": "proposals/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"{ids.size} of {wl.n_walkers} walkers (every {stride}th), sweeps 0-{n_sweeps - 1} of the same "
+                      f"schedule, no branching: {out['proposals']} proposals in {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the anneal runs on one device)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1609_07936_amd import sail as S
+    from paper_1609_07936_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = W.config2()
+    n_sweeps_total = wl.n_sweeps
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, n_sweeps_total)
+    steps, warm = args.steps, args.warmup
+    if steps * SWEEPS_PER_STEP > n_sweeps_total:
+        raise SystemExit("steps exceed the schedule")
+    stream = torch.cuda.current_stream()
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=wl.resync_every)
+    gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
+    for s in range(warm):
+        gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
+    torch.cuda.synchronize()
+    # the timed anneal starts from fresh walkers at sweep 0
+    gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
+    gp.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sweep_ms, launches = gp.sweep_timing(reset=True)
+    elapsed = t1 - t0
+    proposals = wl.n_walkers * wl.omega.size * SWEEPS_PER_STEP * steps
+    value = proposals / elapsed
+    chi2 = gp.read_chi2(stream=stream)
+    # roofline of the sweep kernel: 8 N_tau algorithmic flops per proposal
+    flops_per_launch = 8.0 * wl.tau.size * wl.n_walkers * wl.omega.size * (SWEEPS_PER_STEP * steps / launches)
+    avg_ms = sweep_ms / launches
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    line = {
+        "metric": "walker proposals/s at matched final chi2",
+        "value": value,
+        "unit": "proposals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "production FP64 anneal: 512 omega bins on [0,20], 128 uniform tau on [0.02,3], "
+                        "16384 walkers, T 1e3->1e-2 (x chi2_0) geometric over 20000 sweeps, blocks of 100 sweeps "
+                        "with resync + imprinted branching (fraction 1/4, t = 0.1); seeded two-Lorentzian target, "
+                        "noise 1e-5 F",
+            "n_omega": int(wl.omega.size), "n_tau": int(wl.tau.size), "n_walkers": int(wl.n_walkers),
+            "sweeps_timed": SWEEPS_PER_STEP * steps, "precision": "fp64",
+        },
+        "quality": {
+            "final_chi2_over_chi2_0_median": float(np.median(chi2) / gp.chi2_unit),
+            "final_chi2_over_chi2_0_min": float(chi2.min() / gp.chi2_unit),
+            "at_sweep": SWEEPS_PER_STEP * steps,
+        },
+        "roofline": {
+            "kernel": "k_sweep_f64",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "launches": launches,
+            "sweep_share_of_step": sweep_ms / (elapsed * 1e3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * sail.h -- C ABI of the MI355X (gfx950) implementation of the simulated
+ * annealing inverse Laplace transform of Lutsyshyn & Astrakharchik
+ * ("SAIL", arXiv:1609.07936).
+ *
+ * The library anneals a population of walkers, each a piecewise-constant
+ * spectrum a_j >= 0 on N_omega uniform bins (Sec. 2.1, Eq. spectral-model),
+ * against data F(tau_i) with errors sigma_i.  Every proposal is the
+ * sum-rule preserving two-bin move of Sec. 2.2 (Eqs. update-scheme-p/s/j,
+ * update-delta-p/s); the reconstruction F(tau) is updated incrementally
+ * (Sec. 2.2, F' = r F + dp K_p + ds K_s) and the residue change is reduced
+ * over all tau points and accepted by the Metropolis rule at the current
+ * temperature (Eq. probability-density).  After every block of sweeps the
+ * walkers are branched with imprinting (Sec. 2.5).
+ *
+ * Conventions for every entry point:
+ *  - Plain C types only.  Host pointers are marked "host", device pointers
+ *    "device".  Input arrays are copied; the caller keeps ownership.
+ *  - Output arrays are caller-allocated.
+ *  - Every call returns a sail_status; nothing throws or aborts across the
+ *    ABI.  On an error the call changes no state, and sail_last_error()
+ *    returns a message for the calling thread.
+ *  - A problem is used from one host thread at a time.  Work is enqueued on
+ *    the HIP stream passed as `stream` (NULL means the null stream); calls
+ *    that return host data synchronise that stream.
+ */
+#ifndef SAIL_H
+#define SAIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sail_problem *sail_problem_t;
+
+typedef enum {
+    SAIL_OK = 0,
+    SAIL_EINVAL = 1,      /* an argument is out of range or inconsistent */
+    SAIL_EINFEASIBLE = 2, /* the two sum rules admit no non-negative spectrum */
+    SAIL_ENOMEM = 3,      /* device or host allocation failed */
+    SAIL_EDEVICE = 4,     /* a HIP runtime call failed */
+    SAIL_ENUMERIC = 5,    /* a non-finite residue was found */
+    SAIL_ESTATE = 6       /* call out of order (e.g. run before init) */
+} sail_status;
+
+typedef enum {
+    /* K(omega_j, tau) = d_omega e^{-omega_j tau} / (2 pi): each bin sampled
+     * at its centre. */
+    SAIL_K_POINT = 0,
+    /* K(omega_j, tau) = (1/2 pi) int over bin j of e^{-omega tau} d omega, the
+     * exact bin integral of Eq. (correlation-model). */
+    SAIL_K_BIN_EXACT = 1
+} sail_kernel_mode;
+
+typedef enum {
+    SAIL_FP64 = 0, /* residual loop and residue change in FP64 */
+    SAIL_FP32 = 1  /* residual loop in FP32, resync and final residue in FP64 */
+} sail_precision;
+
+/* Annealing schedule (Sec. 3 gives the defaults noted in brackets). */
+typedef struct {
+    const double *T;        /* host, n_T temperatures; sweep k runs at T[k] */
+    int n_T;
+    int branch_every;       /* sweeps per block; a branching event follows every block [100] */
+    int resync_every;       /* exact recomputation of F and chi^2 every this many sweeps; divides branch_every */
+    double branch_fraction; /* share of walkers given multiplier zero per event [0.25] */
+    double imprint_t;       /* imprint strength t, a <- t a_donor + (1 - t) a [0.1] */
+    double eps0;            /* width of 1 - r: r = 1 - y eps0 (2u - 1), 0 < eps0 < 1 [0.1] */
+    double amp_p;           /* p of Eq. (amplitude-acceptance-adjustment) [1] */
+    int amp_m;              /* m of the same equation, integer >= 0 [2] */
+    double amp_avg;         /* weight of the newest sweep in the running acceptance rate, (0, 1] [0.1] */
+    int walk_len;           /* length of the index-selection walk of Sec. 2.3 (0: uniform) [0] */
+    int t_units;            /* 0: T in units of the starting residue (Sec. 3); 1: absolute */
+} sail_schedule;
+
+/* Fills *s with the defaults above and T = NULL, n_T = 0. */
+void sail_schedule_defaults(sail_schedule *s);
+
+/* Creates a problem (Sec. 2.1).
+ *   omega  host, n_omega >= 3 bin centres, uniform spacing (1e-12 relative)
+ *   tau    host, n_tau >= 1 times >= 0, uniform spacing (1e-12 relative)
+ *   F      host, n_tau data values
+ *   sigma  host, n_tau errors > 0, or NULL for the paper's unweighted residue
+ *   m0, m1 zeroth and first moment of the spectrum, int S and int omega S
+ *          (Sec. 2.2: A = m0 / d_omega, B = m1 / d_omega)
+ *   kernel_mode  a sail_kernel_mode
+ *   device HIP device ordinal the problem lives on
+ * SAIL_EINFEASIBLE if m1 / m0 is not strictly inside (omega_0, omega_{n-1}). */
+sail_status sail_problem_create(const double *omega, int n_omega, const double *tau, int n_tau,
+                                const double *F, const double *sigma, double m0, double m1,
+                                int kernel_mode, int device, sail_problem_t *out);
+
+/* Releases all device and host memory of the problem.  NULL is ignored. */
+void sail_problem_destroy(sail_problem_t p);
+
+/* Allocates n_walkers walkers and sets each to the maximum-entropy spectrum
+ * a_j ~ e^{-lambda omega_j} meeting both sum rules, computes F = K a and the
+ * starting residue chi^2_0 (the unit of temperature, Sec. 3).  `seed` keys
+ * the Philox4x32-10 stream of every random draw.  Resets the sweep and
+ * event logs. */
+sail_status sail_walkers_init(sail_problem_t p, int n_walkers, uint64_t seed, int precision, void *stream);
+
+/* Runs global sweeps [first_sweep, first_sweep + n_sweeps) of `sched`.
+ * A sweep is n_omega proposals per walker.  After sweep k, if (k + 1) is a
+ * multiple of resync_every every walker is renormalised to both sum rules and
+ * its F and chi^2 recomputed; if (k + 1) is a multiple of branch_every the
+ * branching event (k + 1) / branch_every - 1 follows (Sec. 2.5).  Stages may
+ * be run in several calls; the random stream depends only on the global
+ * sweep, proposal and walker indices. */
+sail_status sail_run_schedule(sail_problem_t p, const sail_schedule *sched, int first_sweep, int n_sweeps,
+                              void *stream);
+
+/* Starting residue chi^2_0 (absolute units), or NaN before init. */
+double sail_chi2_unit(sail_problem_t p);
+
+/* Ensemble-mean spectrum, out: host, n_omega doubles (Eq. residue-average
+ * estimated over the walkers). */
+sail_status sail_read_spectrum(sail_problem_t p, double *out, void *stream);
+
+/* Current residue of every walker, out: host, n_walkers doubles. */
+sail_status sail_read_chi2(sail_problem_t p, double *out, void *stream);
+
+/* Histogram of log10 chi^2 over [lo, hi) in n_bins bins (values outside are
+ * clamped into the end bins).  If lo or hi is NaN the ensemble minimum /
+ * maximum is used.  counts: host, n_bins uint64. */
+sail_status sail_read_chi2_hist(sail_problem_t p, int n_bins, double lo, double hi, uint64_t *counts,
+                                void *stream);
+
+/* Walker state, every pointer host and optional (NULL skips it):
+ *   a     [n_walkers][n_omega] spectra a_j (scale folded in)
+ *   F     [n_walkers][n_tau] reconstructions F(tau_i)
+ *   rate  [n_walkers] running acceptance rates */
+sail_status sail_read_state(sail_problem_t p, double *a, double *F, double *rate, void *stream);
+
+/* Branching log of events [0, n_events): Delta, P_r, zero count, status
+ * (0 done, 1 skipped: target unreachable, 2 skipped: threshold tie), and
+ * optionally the multipliers m, [n_events][n_walkers] (requires
+ * sail_set_event_log(p, 1) before the events ran).  Host pointers, any may
+ * be NULL. */
+sail_status sail_read_events(sail_problem_t p, int n_events, double *delta, double *pr, int32_t *z,
+                             int32_t *status, int32_t *m);
+sail_status sail_set_event_log(sail_problem_t p, int keep_multipliers);
+
+/* Per-proposal trace of global sweeps [k0, k1) for every walker into device
+ * buffers laid out [walker][sweep - k0][proposal]:
+ *   dchi2  device, the residue change of the proposal (computed for every
+ *          proposal, also rejected ones)
+ *   flags  device, bit 0 accepted, bit 1 admissible (p != s and a' >= 0)
+ * k0 == k1 switches tracing off.  The buffers must stay valid while sweeps
+ * in the window run.  Tracing selects a slower kernel variant. */
+sail_status sail_set_trace(sail_problem_t p, int k0, int k1, double *dchi2, uint8_t *flags);
+
+/* Timing of the sweep kernel with HIP events on the launch stream: when
+ * enabled, every sweep launch is bracketed by events; sail_sweep_timing
+ * synchronises and returns the summed kernel time and launch count since the
+ * last reset. */
+sail_status sail_set_timing(sail_problem_t p, int enable);
+sail_status sail_sweep_timing(sail_problem_t p, double *total_ms, int64_t *launches, int reset);
+
+/* Device bytes a problem of this size holds (tables plus walker state). */
+size_t sail_footprint_bytes(int n_omega, int n_tau, int n_walkers, int precision);
+
+/* Lanes per walker and tau points per lane the sweep kernel uses. */
+sail_status sail_layout(sail_problem_t p, int *lanes_per_walker, int *tau_per_lane);
+
+const char *sail_status_string(int status);
+const char *sail_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAIL_H */

@@ -69,6 +69,7 @@ class AnnealArgs(ctypes.Structure):
         ("max_events", ctypes.c_int),
         ("ev_delta", ctypes.c_void_p), ("ev_pr", ctypes.c_void_p),
         ("ev_z", ctypes.c_void_p), ("ev_status", ctypes.c_void_p), ("ev_m", ctypes.c_void_p),
+        ("walker_ids", ctypes.c_void_p),
         ("n_near_ties", ctypes.c_int64), ("n_hard_mismatch", ctypes.c_int64),
         ("n_proposals", ctypes.c_int64), ("n_accepted", ctypes.c_int64),
         ("first_mismatch", ctypes.c_int32 * 3),
@@ -253,8 +254,12 @@ def geometric_schedule(t_hi: float, t_lo: float, n_sweeps: int) -> np.ndarray:
 class Anneal:
     """A walker population advanced by the oracle; state lives in numpy."""
 
-    def __init__(self, prob: Problem, sched: Schedule, n_walkers: int, seed: int):
-        self.prob, self.sched, self.n, self.seed = prob, sched, int(n_walkers), int(seed)
+    def __init__(self, prob: Problem, sched: Schedule, n_walkers: int, seed: int, walker_ids=None):
+        """walker_ids: optional global numbers of the walkers held here (a
+        sample of a larger population; stretches without branching only)."""
+        self.prob, self.sched, self.seed = prob, sched, int(seed)
+        self.walker_ids = None if walker_ids is None else np.ascontiguousarray(walker_ids, dtype=np.int32)
+        self.n = int(n_walkers) if walker_ids is None else int(self.walker_ids.size)
         No, Nt = prob.omega.size, prob.tau.size
         self.a0, self.lam = init_spectrum(prob.omega, prob.A, prob.B)
         self.a = np.zeros((self.n, No))
@@ -285,6 +290,7 @@ class Anneal:
         g.max_events = n_ev
         g.ev_delta, g.ev_pr, g.ev_z = _p(self.ev_delta), _p(self.ev_pr), _p(self.ev_z)
         g.ev_status, g.ev_m = _p(self.ev_status), _p(self.ev_m)
+        g.walker_ids = _p(self.walker_ids)
         lib().or_walkers_init(ctypes.byref(g), _p(self.a0), _p(self.a), _p(self.F), _p(self.chi2),
                               _p(self.rate))
         self.chi2_unit = float(self.chi2[0])  # Sec. 3: the starting residue is the unit of T
@@ -318,6 +324,8 @@ class Anneal:
         g.n_near_ties = g.n_hard_mismatch = g.n_proposals = g.n_accepted = 0
         rc = lib().or_anneal(ctypes.byref(g), int(k0), int(k1), _p(self.a), _p(self.F), _p(self.chi2),
                              _p(self.rate))
+        if rc == 2:
+            raise ValueError("a walker sample cannot cross a branching event")
         if rc != 0:
             raise ValueError("or_anneal rejected its arguments")
         out.update(near_ties=g.n_near_ties, hard_mismatch=g.n_hard_mismatch, proposals=g.n_proposals,

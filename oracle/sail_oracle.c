@@ -363,6 +363,10 @@ typedef struct {
     int max_events;
     double *ev_delta, *ev_pr;
     int32_t *ev_z, *ev_status, *ev_m; /* ev_m is [event][walker] */
+    /* optional global walker numbers of the rows held here (NULL: row l is
+     * walker l); lets a test replay a sample of a large population.  Only
+     * valid for stretches without a branching event. */
+    const int32_t *walker_ids;
     /* results */
     int64_t n_near_ties, n_hard_mismatch, n_proposals, n_accepted;
     int32_t first_mismatch[3]; /* walker, sweep, proposal of the earliest hard mismatch, or -1 */
@@ -380,6 +384,7 @@ static void walker_sweeps(const or_anneal_args *g, int l, int k0, int k1,
 {
     const int No = g->n_omega, Nt = g->n_tau;
     const double *omega = g->omega, *K = g->K, *w = g->w, *Ft = g->Ft;
+    const uint32_t gl = g->walker_ids ? (uint32_t)g->walker_ids[l] : (uint32_t)l;
     for (int k = k0; k < k1; ++k) {
         double Tabs = g->T[k] * g->chi2_unit;
         /* Eq. (amplitude-acceptance-adjustment).  Reading: the "ongoing"
@@ -396,12 +401,12 @@ static void walker_sweeps(const or_anneal_args *g, int l, int k0, int k1,
         size_t toff = traced ? ((size_t)l * (size_t)(g->trace_k1 - g->trace_k0) + (size_t)(k - g->trace_k0)) * (size_t)No : 0;
         for (int q = 0; q < No; ++q) {
             uint32_t x[4];
-            draw(g->seed, (uint32_t)q, (uint32_t)k, (uint32_t)l, OR_STREAM_PROPOSAL, x);
+            draw(g->seed, (uint32_t)q, (uint32_t)k, gl, OR_STREAM_PROPOSAL, x);
             int p = index_of(x[0], No), s = index_of(x[1], No);
             /* Sec. 2.3: truncated independence walk on P(j) = a_j / A */
             for (int st = 1; st <= g->walk_len; ++st) {
                 uint32_t y4[4];
-                draw(g->seed, (uint32_t)q, (uint32_t)k, (uint32_t)l, (uint32_t)st, y4);
+                draw(g->seed, (uint32_t)q, (uint32_t)k, gl, (uint32_t)st, y4);
                 int pc = index_of(y4[0], No), sc = index_of(y4[2], No);
                 if (u01(y4[1]) * a[p] < a[pc]) p = pc;
                 if (u01(y4[3]) * a[s] < a[sc]) s = sc;
@@ -535,6 +540,7 @@ int or_anneal(or_anneal_args *g, int k0, int k1, double *a, double *F, double *c
     const int n = g->n_walkers, No = g->n_omega, Nt = g->n_tau;
     if (k0 < 0 || k1 > g->n_T || k0 > k1) return 1;
     if (g->resync_every <= 0 || g->branch_every <= 0 || g->branch_every % g->resync_every != 0) return 1;
+    if (g->walker_ids && k1 / g->branch_every > k0 / g->branch_every) return 2;
     walker_log *lg = (walker_log *)calloc((size_t)n, sizeof(walker_log));
     for (int l = 0; l < n; ++l) { lg[l].fk = -1; lg[l].fq = -1; }
     int k = k0;

@@ -1,0 +1,245 @@
+"""Python binding of libsail (the gfx950 SAIL annealing library).
+
+Argument marshalling only: every step of the anneal runs in the HIP
+kernels behind the C ABI declared in include/sail.h.  PyTorch supplies the
+HIP stream (and device buffers for the optional trace).  Importing this
+module fails loudly when the built library is missing; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsail.so")
+
+SAIL_K_POINT, SAIL_K_BIN_EXACT = 0, 1
+SAIL_FP64, SAIL_FP32 = 0, 1
+
+
+class SailError(RuntimeError):
+    def __init__(self, status: int, what: str, message: str):
+        super().__init__(f"{what}: {message} (status {status})")
+        self.status = status
+
+
+class ScheduleC(ctypes.Structure):
+    _fields_ = [
+        ("T", ctypes.c_void_p), ("n_T", ctypes.c_int),
+        ("branch_every", ctypes.c_int), ("resync_every", ctypes.c_int),
+        ("branch_fraction", ctypes.c_double), ("imprint_t", ctypes.c_double),
+        ("eps0", ctypes.c_double), ("amp_p", ctypes.c_double), ("amp_m", ctypes.c_int),
+        ("amp_avg", ctypes.c_double), ("walk_len", ctypes.c_int), ("t_units", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsail.so is not built ({LIB_PATH}); run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    st = ctypes.c_int
+    L.sail_schedule_defaults.argtypes = [ctypes.POINTER(ScheduleC)]
+    L.sail_schedule_defaults.restype = None
+    L.sail_problem_create.argtypes = [P, I, P, I, P, P, D, D, I, I, ctypes.POINTER(P)]
+    L.sail_problem_create.restype = st
+    L.sail_problem_destroy.argtypes = [P]
+    L.sail_problem_destroy.restype = None
+    L.sail_walkers_init.argtypes = [P, I, ctypes.c_uint64, I, P]
+    L.sail_walkers_init.restype = st
+    L.sail_run_schedule.argtypes = [P, ctypes.POINTER(ScheduleC), I, I, P]
+    L.sail_run_schedule.restype = st
+    L.sail_chi2_unit.argtypes = [P]
+    L.sail_chi2_unit.restype = D
+    L.sail_read_spectrum.argtypes = [P, P, P]
+    L.sail_read_spectrum.restype = st
+    L.sail_read_chi2.argtypes = [P, P, P]
+    L.sail_read_chi2.restype = st
+    L.sail_read_chi2_hist.argtypes = [P, I, D, D, P, P]
+    L.sail_read_chi2_hist.restype = st
+    L.sail_read_state.argtypes = [P, P, P, P, P]
+    L.sail_read_state.restype = st
+    L.sail_read_events.argtypes = [P, I, P, P, P, P, P]
+    L.sail_read_events.restype = st
+    L.sail_set_event_log.argtypes = [P, I]
+    L.sail_set_event_log.restype = st
+    L.sail_set_trace.argtypes = [P, I, I, P, P]
+    L.sail_set_trace.restype = st
+    L.sail_set_timing.argtypes = [P, I]
+    L.sail_set_timing.restype = st
+    L.sail_sweep_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), I]
+    L.sail_sweep_timing.restype = st
+    L.sail_footprint_bytes.argtypes = [I, I, I, I]
+    L.sail_footprint_bytes.restype = ctypes.c_size_t
+    L.sail_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.sail_layout.restype = st
+    L.sail_status_string.argtypes = [I]
+    L.sail_status_string.restype = ctypes.c_char_p
+    L.sail_last_error.argtypes = []
+    L.sail_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        msg = lib().sail_last_error().decode(errors="replace")
+        raise SailError(status, what, msg or lib().sail_status_string(status).decode())
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _stream_handle(stream) -> int | None:
+    """A HIP stream handle: an int, a torch.cuda.Stream, or None for torch's
+    current stream (the null stream without torch)."""
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return int(torch.cuda.current_stream().cuda_stream) or None
+        except Exception:
+            return None
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    return int(stream.cuda_stream) or None
+
+
+def footprint_bytes(n_omega: int, n_tau: int, n_walkers: int, precision: int = SAIL_FP64) -> int:
+    return int(lib().sail_footprint_bytes(n_omega, n_tau, n_walkers, precision))
+
+
+class Schedule:
+    """Annealing schedule; defaults are those of Sec. 3 of the paper plus the
+    running-average weight of the acceptance rate."""
+
+    def __init__(self, T, branch_every=100, resync_every=100, branch_fraction=0.25, imprint_t=0.1, eps0=0.1,
+                 amp_p=1.0, amp_m=2, amp_avg=0.1, walk_len=0, t_units=0):
+        self.T = _f64(T)
+        self.c = ScheduleC()
+        lib().sail_schedule_defaults(ctypes.byref(self.c))
+        c = self.c
+        c.T, c.n_T = _p(self.T), self.T.size
+        c.branch_every, c.resync_every = int(branch_every), int(resync_every)
+        c.branch_fraction, c.imprint_t, c.eps0 = float(branch_fraction), float(imprint_t), float(eps0)
+        c.amp_p, c.amp_m, c.amp_avg = float(amp_p), int(amp_m), float(amp_avg)
+        c.walk_len, c.t_units = int(walk_len), int(t_units)
+
+    @property
+    def n_sweeps(self) -> int:
+        return int(self.T.size)
+
+
+class Problem:
+    """One inversion on one GPU (see sail_problem_create)."""
+
+    def __init__(self, omega, tau, F, sigma, m0: float, m1: float, mode: int = SAIL_K_POINT, device: int = 0):
+        self.omega, self.tau, self.F = _f64(omega), _f64(tau), _f64(F)
+        self.sigma = None if sigma is None else _f64(sigma)
+        self.n_omega, self.n_tau = self.omega.size, self.tau.size
+        self.n_walkers = 0
+        h = ctypes.c_void_p()
+        _check(lib().sail_problem_create(_p(self.omega), self.n_omega, _p(self.tau), self.n_tau, _p(self.F),
+                                         _p(self.sigma), float(m0), float(m1), int(mode), int(device),
+                                         ctypes.byref(h)), "sail_problem_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().sail_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_walkers(self, n_walkers: int, seed: int, precision: int = SAIL_FP64, stream=None) -> float:
+        _check(lib().sail_walkers_init(self._h, int(n_walkers), int(seed), int(precision), _stream_handle(stream)),
+               "sail_walkers_init")
+        self.n_walkers = int(n_walkers)
+        return self.chi2_unit
+
+    @property
+    def chi2_unit(self) -> float:
+        return float(lib().sail_chi2_unit(self._h))
+
+    def run(self, sched: Schedule, first_sweep: int, n_sweeps: int, stream=None) -> None:
+        _check(lib().sail_run_schedule(self._h, ctypes.byref(sched.c), int(first_sweep), int(n_sweeps),
+                                       _stream_handle(stream)), "sail_run_schedule")
+
+    def read_spectrum(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.n_omega)
+        _check(lib().sail_read_spectrum(self._h, _p(out), _stream_handle(stream)), "sail_read_spectrum")
+        return out
+
+    def read_chi2(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.n_walkers)
+        _check(lib().sail_read_chi2(self._h, _p(out), _stream_handle(stream)), "sail_read_chi2")
+        return out
+
+    def read_chi2_hist(self, n_bins: int = 64, lo: float = float("nan"), hi: float = float("nan"),
+                       stream=None) -> np.ndarray:
+        out = np.zeros(n_bins, dtype=np.uint64)
+        _check(lib().sail_read_chi2_hist(self._h, int(n_bins), float(lo), float(hi), _p(out),
+                                         _stream_handle(stream)), "sail_read_chi2_hist")
+        return out
+
+    def read_state(self, stream=None) -> dict:
+        a = np.zeros((self.n_walkers, self.n_omega))
+        F = np.zeros((self.n_walkers, self.n_tau))
+        rate = np.zeros(self.n_walkers)
+        _check(lib().sail_read_state(self._h, _p(a), _p(F), _p(rate), _stream_handle(stream)), "sail_read_state")
+        return {"a": a, "F": F, "rate": rate}
+
+    def set_event_log(self, keep_multipliers: bool) -> None:
+        _check(lib().sail_set_event_log(self._h, int(bool(keep_multipliers))), "sail_set_event_log")
+
+    def read_events(self, n_events: int, multipliers: bool = False) -> dict:
+        d = np.zeros(n_events)
+        pr = np.zeros(n_events)
+        z = np.zeros(n_events, dtype=np.int32)
+        stt = np.zeros(n_events, dtype=np.int32)
+        m = np.zeros((n_events, self.n_walkers), dtype=np.int32) if multipliers else None
+        _check(lib().sail_read_events(self._h, int(n_events), _p(d), _p(pr), _p(z), _p(stt), _p(m)),
+               "sail_read_events")
+        out = {"delta": d, "pr": pr, "z": z, "status": stt}
+        if multipliers:
+            out["m"] = m
+        return out
+
+    def set_trace(self, k0: int, k1: int, dchi2_ptr: int = 0, flags_ptr: int = 0) -> None:
+        """Device buffers [n_walkers][k1 - k0][n_omega] (float64 and uint8)."""
+        _check(lib().sail_set_trace(self._h, int(k0), int(k1), ctypes.c_void_p(dchi2_ptr or None),
+                                    ctypes.c_void_p(flags_ptr or None)), "sail_set_trace")
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib().sail_set_timing(self._h, int(bool(enable))), "sail_set_timing")
+
+    def sweep_timing(self, reset: bool = False) -> tuple[float, int]:
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().sail_sweep_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(bool(reset))),
+               "sail_sweep_timing")
+        return ms.value, n.value
+
+    def layout(self) -> tuple[int, int]:
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sail_layout(self._h, ctypes.byref(a), ctypes.byref(b)), "sail_layout")
+        return a.value, b.value

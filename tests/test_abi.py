@@ -1,0 +1,78 @@
+"""The C-ABI library loads on the CPU, exports every symbol include/sail.h
+declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "sail.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sail_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1609_07936_amd import sail
+    sail.lib()
+    return sail
+
+
+def test_every_declared_symbol_is_exported(S):
+    names = _declared()
+    assert len(names) >= 19
+    missing = [n for n in names if not hasattr(S.lib(), n)]
+    assert not missing, missing
+
+
+def test_host_only_entry_points(S):
+    L = S.lib()
+    sc = S.ScheduleC()
+    L.sail_schedule_defaults(ctypes.byref(sc))
+    # Sec. 3 defaults: blocks of 100 sweeps, a quarter branched, t = 0.1, p = 1, m = 2
+    assert (sc.branch_every, sc.branch_fraction, sc.imprint_t, sc.amp_p, sc.amp_m) == (100, 0.25, 0.1, 1.0, 2)
+    assert L.sail_status_string(0) == b"ok" and L.sail_status_string(2) == b"sum rules infeasible"
+    fb = S.footprint_bytes(512, 128, 16384)
+    assert 16384 * (512 + 256) * 8 <= fb < 16384 * (512 + 256) * 8 * 1.2
+    assert S.footprint_bytes(0, 128, 10) == 0
+
+
+def test_invalid_arguments_rejected_before_device(S):
+    om = (np.arange(64) + 0.5) * (10 / 64)
+    tau = 0.05 * np.arange(1, 33)
+    F = np.exp(-tau)
+    with pytest.raises(S.SailError) as e:
+        S.Problem(om[:2], tau, F, None, 1.0, 2.0)
+    assert e.value.status == 1
+    with pytest.raises(S.SailError) as e:
+        S.Problem(om, tau, F, None, 1.0, 20.0)  # mean frequency outside the window
+    assert e.value.status == 2
+    with pytest.raises(S.SailError) as e:
+        S.Problem(om, tau, F, -np.ones(32), 1.0, 2.0)
+    assert e.value.status == 1
+    bad = om.copy()
+    bad[5] += 1e-3
+    with pytest.raises(S.SailError) as e:
+        S.Problem(bad, tau, F, None, 1.0, 2.0)
+    assert e.value.status == 1
+    Fn = F.copy()
+    Fn[3] = np.nan
+    with pytest.raises(S.SailError) as e:
+        S.Problem(om, tau, Fn, None, 1.0, 2.0)
+    assert e.value.status == 1
+
+
+def test_no_device_reports_device_error(S):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    om = (np.arange(64) + 0.5) * (10 / 64)
+    tau = 0.05 * np.arange(1, 33)
+    with pytest.raises(S.SailError) as e:
+        S.Problem(om, tau, np.exp(-tau), None, 1.0, 2.0)
+    assert e.value.status == 4

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded
+inputs and the same Philox stream.
+
+The bar (derived in the design doc from the arithmetic of the residue change):
+  * |dchi2_gpu - dchi2_oracle| <= 1e-12 * M for every traced proposal, M the
+    condition scale sum_i w_i (|r-1||F_i| + |dp|K_pi + |ds|K_si)(2|F_i| + 2|Ft_i| + |dF_i|);
+  * identical accept decisions, except near-ties (decisions whose margin lies
+    inside the 1e-12 band), which the oracle logs and adopts;
+  * identical branching multipliers, targets and donors;
+  * final residues within 1e-9 relative and the averaged spectrum within
+    1e-10 in L1 (sum_j |da_j| d_omega, against a unit zeroth moment).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1609_07936_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1609_07936_amd import sail
+    sail.lib()
+    return sail
+
+
+def _pair(S, wl, n_walkers, seed, sched_kw=None, mode=0, sigma=True, T=None):
+    sched_kw = sched_kw or {}
+    if T is None:
+        T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    sg = wl.sigma if sigma else None
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, sg, wl.m0, wl.m1, mode)
+    gp.init_walkers(n_walkers, seed)
+    op = O.Problem(wl.omega, wl.tau, wl.Ft, sg, wl.m0, wl.m1, mode)
+    return gp, S.Schedule(T, **sched_kw), op, O.Schedule(T, **sched_kw)
+
+
+def _trace_buffers(n, n_sweeps, n_omega):
+    import torch
+    d = torch.zeros((n, n_sweeps, n_omega), dtype=torch.float64, device="cuda")
+    f = torch.zeros((n, n_sweeps, n_omega), dtype=torch.uint8, device="cuda")
+    return d, f
+
+
+def _check_trace(g_d, g_f, out):
+    cond = out["cond"]
+    err = np.abs(g_d - out["dchi2"])
+    bad = err > 1e-12 * cond
+    assert not bad.any(), f"{bad.sum()} proposals outside 1e-12 M; worst {np.max(err / np.maximum(cond, 1e-300)):.3e}"
+    assert out["hard_mismatch"] == 0, f"hard mismatches at {out['first_mismatch']}"
+    # after adopting near-ties the accept bits agree everywhere
+    np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
+
+
+def _anneal_lockstep(S, wl, n_walkers, seed, n_sweeps, sched_kw=None, mode=0, sigma=True, T=None):
+    import torch
+    gp, gs, op, osch = _pair(S, wl, n_walkers, seed, sched_kw, mode, sigma, T)
+    an = O.Anneal(op, osch, n_walkers, seed)
+    assert abs(gp.chi2_unit / an.chi2_unit - 1) < 1e-12
+    gp.set_event_log(True)
+    d, f = _trace_buffers(n_walkers, n_sweeps, wl.omega.size)
+    gp.set_trace(0, n_sweeps, d.data_ptr(), f.data_ptr())
+    gp.run(gs, 0, n_sweeps)
+    torch.cuda.synchronize()
+    g_d, g_f = d.cpu().numpy(), f.cpu().numpy()
+    out = an.run(0, n_sweeps, trace=(0, n_sweeps), replay=g_f)
+    _check_trace(g_d, g_f, out)
+    n_ev = n_sweeps // osch.branch_every
+    if n_ev:
+        ev = gp.read_events(n_ev, multipliers=True)
+        np.testing.assert_array_equal(ev["status"], an.ev_status[:n_ev])
+        np.testing.assert_array_equal(ev["m"], an.ev_m[:n_ev])
+        np.testing.assert_array_equal(ev["z"], an.ev_z[:n_ev])
+        done = ev["status"] == 0
+        np.testing.assert_allclose(ev["delta"][done], an.ev_delta[:n_ev][done], rtol=1e-9)
+    chi2 = gp.read_chi2()
+    np.testing.assert_allclose(chi2, an.chi2, rtol=1e-9)
+    st = gp.read_state()
+    np.testing.assert_allclose(st["a"], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
+    np.testing.assert_allclose(st["F"], an.F, rtol=1e-12)
+    spec = gp.read_spectrum()
+    dw = wl.omega[1] - wl.omega[0]
+    assert np.sum(np.abs(spec - an.mean_spectrum())) * dw <= 1e-10 * wl.m0
+    return gp, an, out
+
+
+def test_config1_full_anneal_lockstep(S):
+    """Config 1 end to end: 64 walkers x 2000 sweeps x 64 proposals, 20
+    branching events; every proposal traced and compared."""
+    wl = W.config1()
+    gp, an, out = _anneal_lockstep(S, wl, 64, wl.seed, wl.n_sweeps)
+    assert out["proposals"] == 64 * 2000 * 64
+    assert 0.2 < out["accepted"] / out["proposals"] < 0.8
+    assert np.all(an.ev_status[:20] == 0)
+
+
+@pytest.mark.parametrize("case", ["ragged", "bin_exact_unweighted", "single_tau", "two_walkers", "wide"])
+def test_edge_shapes_lockstep(S, case):
+    """Ragged walker counts and tau padding, the exact-bin kernel with the
+    paper's unweighted residue, one tau point, the smallest population, and
+    the widest lane layout."""
+    rng = np.random.default_rng(77)
+    tgt = W.Target([1.2, 3.0], [0.3, 0.6], [0.5, 0.5], 6.0)
+    if case == "ragged":
+        wl = W.make("r", 6.0, 50, W.uniform_tau(0.05, 1.5, 21), tgt, 1e-4, 3, 37, 300, 1e2, 1e-3, 50, 25, 5)
+        kw, mode, sigma = dict(branch_every=50, resync_every=25), 0, True
+    elif case == "bin_exact_unweighted":
+        wl = W.make("b", 6.0, 40, W.uniform_tau(0.0, 2.0, 33), tgt, 1e-4, 4, 24, 200, 1e1, 1e-4, 100, 50, 6)
+        kw, mode, sigma = dict(branch_every=100, resync_every=50), 1, False
+    elif case == "single_tau":
+        wl = W.make("s", 6.0, 16, np.array([0.4]), tgt, 1e-3, 5, 8, 100, 1e1, 1e-2, 50, 50, 7)
+        kw, mode, sigma = dict(branch_every=50, resync_every=50, branch_fraction=0.25), 0, True
+    elif case == "two_walkers":
+        wl = W.make("t", 6.0, 24, W.uniform_tau(0.1, 1.0, 10), tgt, 1e-4, 6, 2, 100, 1e1, 1e-2, 50, 50, 8)
+        kw, mode, sigma = dict(branch_every=50, resync_every=50, branch_fraction=0.5), 0, True
+    else:
+        wl = W.make("w", 20.0, 1024, W.uniform_tau(0.02, 3.0, 256), W.two_peak_random(rng, 20.0), 1e-5, 9, 48, 4,
+                    1e3, 1e-2, 2, 1, 10, n_quad=20000)
+        kw, mode, sigma = dict(branch_every=2, resync_every=1), 0, True
+    _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma)
+
+
+def test_config2_full_size_sampled_lockstep(S):
+    """Config 2 at full size (16384 walkers, 512 bins, 128 times) in the
+    launch configuration the benchmark times: three traced sweeps, checked on
+    a sample of walkers that the oracle replays one by one."""
+    import torch
+    wl = W.config2()
+    n = wl.n_walkers
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(n, wl.seed)
+    gs = S.Schedule(T)
+    ns = 3
+    d, f = _trace_buffers(n, ns, wl.omega.size)
+    gp.set_trace(0, ns, d.data_ptr(), f.data_ptr())
+    gp.run(gs, 0, ns)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    ids = np.unique(np.concatenate([[0, 1, 7, 8, 63, 64, 4095, 8191, 16383], rng.choice(n, 23, replace=False)]))
+    g_d, g_f = d[ids].cpu().numpy(), f[ids].cpu().numpy()
+    del d, f
+    op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    an = O.Anneal(op, O.Schedule(T), n, wl.seed, walker_ids=ids)
+    assert abs(gp.chi2_unit / an.chi2_unit - 1) < 1e-12
+    out = an.run(0, ns, trace=(0, ns), replay=g_f)
+    _check_trace(g_d, g_f, out)
+    st = gp.read_state()
+    np.testing.assert_allclose(st["F"][ids], an.F, rtol=1e-12)
+    np.testing.assert_allclose(st["a"][ids], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
+
+
+def test_config2_full_size_branching_event(S):
+    """The first branching event of config 2 at full size: the GPU's
+    multipliers equal the oracle's solve on the same residues, and every
+    target holds t a_donor + (1 - t) a_target afterwards."""
+    wl = W.config2()
+    n = wl.n_walkers
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    runs = {}
+    for name, be in (("plain", 10 ** 6), ("branch", 100)):
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.init_walkers(n, wl.seed)
+        gp.set_event_log(True)
+        gp.run(S.Schedule(T, branch_every=be), 0, 100)
+        runs[name] = (gp, gp.read_chi2(), gp.read_state())
+    chi2_pre, st_pre = runs["plain"][1], runs["plain"][2]
+    gpb, _, st_post = runs["branch"]
+    ev = gpb.read_events(1, multipliers=True)
+    xi = O.branch_xi(wl.seed, 0, n)
+    res = O.branch_solve(chi2_pre, xi, 0.25)
+    assert res["status"] == 0 and ev["status"][0] == 0
+    np.testing.assert_array_equal(ev["m"][0], res["m"])
+    assert ev["z"][0] == res["z"]
+    tg, dn = O.branch_pairs(res["m"])
+    t = 0.1
+    expect = t * st_pre["a"][dn] + (1 - t) * st_pre["a"][tg]
+    np.testing.assert_allclose(st_post["a"][tg], expect, rtol=1e-15, atol=0)
+    keep = np.setdiff1d(np.arange(n), tg)
+    np.testing.assert_array_equal(st_post["a"][keep], st_pre["a"][keep])
+
+
+def test_deterministic_and_stageable(S):
+    """Two identical runs give identical bits, and a run split in stages
+    equals the run in one call."""
+    wl = W.config1()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    res = []
+    for stages in ([(0, 400)], [(0, 400)], [(0, 37), (37, 163), (163, 400)]):
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.init_walkers(64, wl.seed)
+        sched = S.Schedule(T)
+        for k0, k1 in stages:
+            gp.run(sched, k0, k1 - k0)
+        st = gp.read_state()
+        res.append((gp.read_chi2(), st["a"], st["F"]))
+    for r in res[1:]:
+        for x, y in zip(res[0], r):
+            assert np.array_equal(x, y)
+
+
+def test_outputs_match_oracle_definitions(S):
+    wl = W.config1()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(64, wl.seed)
+    gp.run(S.Schedule(T), 0, 300)
+    chi2 = gp.read_chi2()
+    st = gp.read_state()
+    np.testing.assert_allclose(gp.read_spectrum(), np.mean(st["a"], axis=0), rtol=1e-13)
+    lo, hi = np.log10(chi2.min()), np.log10(chi2.max())
+    h_auto = gp.read_chi2_hist(64)
+    h_ref = O.chi2_hist(chi2, 64, lo, hi)
+    np.testing.assert_array_equal(h_auto, h_ref)
+    h2 = gp.read_chi2_hist(10, lo - 1, hi + 1)
+    np.testing.assert_array_equal(h2, O.chi2_hist(chi2, 10, lo - 1, hi + 1))
+
+
+def test_errors_leave_problem_usable(S):
+    wl = W.config1()
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    with pytest.raises(S.SailError):
+        gp.run(S.Schedule(np.ones(10)), 0, 10)  # before init
+    gp.init_walkers(8, 1)
+    with pytest.raises(S.SailError):
+        gp.run(S.Schedule(np.ones(10)), 5, 10)  # past the schedule
+    with pytest.raises(S.SailError):
+        gp.run(S.Schedule(np.ones(10), branch_every=30, resync_every=7), 0, 10)
+    with pytest.raises(S.SailError):
+        gp.run(S.Schedule(np.ones(10), eps0=1.5), 0, 10)
+    with pytest.raises(S.SailError):
+        gp.run(S.Schedule(np.full(10, -1.0)), 0, 10)
+    gp.run(S.Schedule(np.ones(10)), 0, 10)
+    assert np.all(np.isfinite(gp.read_chi2()))
