@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed blocks of 100 sweeps (200 = the whole anneal)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c2"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3"],
+                    help="c2: FP64 loop (default); c3: FP32 loop with FP64 resync every 50 sweeps")
     ap.add_argument("--cpu-sample-walkers", type=int, default=1024)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -69,7 +70,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = W.config2()
+    fp32 = args.config == "c3"
+    wl = W.config3() if fp32 else W.config2()
+    precision = S.SAIL_FP32 if fp32 else S.SAIL_FP64
     n_sweeps_total = wl.n_sweeps
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, n_sweeps_total)
     steps, warm = args.steps, args.warmup
@@ -78,12 +81,12 @@ def main():
     stream = torch.cuda.current_stream()
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=wl.resync_every)
-    gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
+    gp.init_walkers(wl.n_walkers, wl.seed, precision=precision, stream=stream)
     for s in range(warm):
         gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
     torch.cuda.synchronize()
     # the timed anneal starts from fresh walkers at sweep 0
-    gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
+    gp.init_walkers(wl.n_walkers, wl.seed, precision=precision, stream=stream)
     gp.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -100,6 +103,7 @@ def main():
     flops_per_launch = 8.0 * wl.tau.size * wl.n_walkers * wl.omega.size * (SWEEPS_PER_STEP * steps / launches)
     avg_ms = sweep_ms / launches
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    peak = FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS
     line = {
         "metric": "walker proposals/s at matched final chi2",
         "value": value,
@@ -111,15 +115,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "production FP64 anneal: 512 omega bins on [0,20], 128 uniform tau on [0.02,3], "
+            "workload": ("FP32-loop variant (FP64 resync + renormalisation every 50 sweeps) of the " if fp32 else
+                         "production FP64 anneal: ") +
+                        "512 omega bins on [0,20], 128 uniform tau on [0.02,3], "
                         "16384 walkers, T 1e3->1e-2 (x chi2_0) geometric over 20000 sweeps, blocks of 100 sweeps "
                         "with resync + imprinted branching (fraction 1/4, t = 0.1); seeded two-Lorentzian target, "
                         "noise 1e-5 F",
             "n_omega": int(wl.omega.size), "n_tau": int(wl.tau.size), "n_walkers": int(wl.n_walkers),
-            "sweeps_timed": SWEEPS_PER_STEP * steps, "precision": "fp64",
+            "sweeps_timed": SWEEPS_PER_STEP * steps, "precision": "fp32 loop" if fp32 else "fp64",
         },
         "quality": {
             "final_chi2_over_chi2_0_median": float(np.median(chi2) / gp.chi2_unit),
@@ -127,12 +133,12 @@ def main():
             "at_sweep": SWEEPS_PER_STEP * steps,
         },
         "roofline": {
-            "kernel": "k_sweep_f64",
+            "kernel": "k_sweep<float>" if fp32 else "k_sweep<double>",
             "bound": "alu",
             "achieved": achieved,
-            "peak": FP64_PEAK_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS,
+            "frac": achieved / peak,
             "traffic": None,
             "avg_launch_ms": avg_ms,
             "launches": launches,

@@ -236,3 +236,51 @@ def test_errors_leave_problem_usable(S):
         gp.run(S.Schedule(np.full(10, -1.0)), 0, 10)
     gp.run(S.Schedule(np.ones(10)), 0, 10)
     assert np.all(np.isfinite(gp.read_chi2()))
+
+
+def test_fp32_loop_first_sweeps_within_fp32_bar(S):
+    """FP32 residual loop (config 3's variant): every proposal of the first two
+    sweeps against the FP64 oracle.  The loop carries Phi, G and the columns
+    in FP32, so the bar is (TPL + log2 L + 8) u_32 M <= 1e-5 M; decisions whose
+    margin falls inside that band are adopted by the oracle."""
+    import torch
+    wl = W.config1()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(64, wl.seed, precision=S.SAIL_FP32)
+    lanes, tpl = gp.layout()
+    assert tpl == 32
+    ns = 2
+    d, f = _trace_buffers(64, ns, wl.omega.size)
+    gp.set_trace(0, ns, d.data_ptr(), f.data_ptr())
+    gp.run(S.Schedule(T), 0, ns)
+    torch.cuda.synchronize()
+    g_d, g_f = d.cpu().numpy(), f.cpu().numpy()
+    an = O.Anneal(O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1), O.Schedule(T), 64, wl.seed)
+    out = an.run(0, ns, trace=(0, ns), replay=g_f, band=1e-5)
+    assert out["hard_mismatch"] == 0, out["first_mismatch"]
+    err = np.abs(g_d - out["dchi2"])
+    assert np.all(err <= 1e-5 * out["cond"]), np.max(err / out["cond"])
+    np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
+
+
+def test_fp32_anneal_quality_against_fp64(S):
+    """A whole config-1 anneal with the FP32 loop (FP64 resync every 50 sweeps)
+    lands in the same residue range as the FP64 path, and the FP64 resync keeps
+    both sum rules to rounding."""
+    wl = W.config1()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    res = {}
+    for prec, rs in ((S.SAIL_FP64, 100), (S.SAIL_FP32, 50)):
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.init_walkers(64, wl.seed, precision=prec)
+        gp.run(S.Schedule(T, resync_every=rs), 0, wl.n_sweeps)
+        res[prec] = (gp.read_chi2() / gp.chi2_unit, gp.read_state()["a"], gp.read_spectrum())
+    c64, a64, s64 = res[S.SAIL_FP64]
+    c32, a32, s32 = res[S.SAIL_FP32]
+    assert 0.3 < np.median(c32) / np.median(c64) < 3.0
+    dw = wl.omega[1] - wl.omega[0]
+    A, B = wl.m0 / dw, wl.m1 / dw
+    assert np.max(np.abs(a32.sum(axis=1) - A)) <= 1e-12 * A
+    assert np.max(np.abs((a32 * wl.omega).sum(axis=1) - B)) <= 1e-12 * B
+    assert np.sum(np.abs(s32 - s64)) * dw < 0.5
