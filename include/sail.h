@@ -160,6 +160,17 @@ sail_status sail_set_trace(sail_problem_t p, int k0, int k1, double *dchi2, uint
 sail_status sail_set_timing(sail_problem_t p, int enable);
 sail_status sail_sweep_timing(sail_problem_t p, double *total_ms, int64_t *launches, int reset);
 
+/* Checkpoint of the walker population (spectra, reconstructions, scales,
+ * residues, acceptance rates, seed and residue unit); with the counter-based
+ * random stream, export -> import -> continue is bit-identical to an
+ * uninterrupted run.  Export: buf host; with buf == NULL only *bytes is set
+ * to the size needed; otherwise *bytes is the capacity of buf on entry and
+ * the size written on return.  Import: buf host, bytes its size; the problem
+ * must already hold walkers of the same count, layout and precision
+ * (sail_walkers_init). */
+sail_status sail_state_export(sail_problem_t p, void *buf, size_t *bytes, void *stream);
+sail_status sail_state_import(sail_problem_t p, const void *buf, size_t bytes, void *stream);
+
 /* Device bytes a problem of this size holds (tables plus walker state). */
 size_t sail_footprint_bytes(int n_omega, int n_tau, int n_walkers, int precision);
 

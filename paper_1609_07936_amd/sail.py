@@ -82,6 +82,10 @@ def lib() -> ctypes.CDLL:
     L.sail_footprint_bytes.restype = ctypes.c_size_t
     L.sail_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.sail_layout.restype = st
+    L.sail_state_export.argtypes = [P, P, ctypes.POINTER(ctypes.c_size_t), P]
+    L.sail_state_export.restype = st
+    L.sail_state_import.argtypes = [P, P, ctypes.c_size_t, P]
+    L.sail_state_import.restype = st
     L.sail_status_string.argtypes = [I]
     L.sail_status_string.restype = ctypes.c_char_p
     L.sail_last_error.argtypes = []
@@ -238,6 +242,17 @@ class Problem:
         _check(lib().sail_sweep_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(bool(reset))),
                "sail_sweep_timing")
         return ms.value, n.value
+
+    def state_export(self, stream=None) -> bytes:
+        n = ctypes.c_size_t(0)
+        _check(lib().sail_state_export(self._h, None, ctypes.byref(n), _stream_handle(stream)), "sail_state_export")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().sail_state_export(self._h, buf, ctypes.byref(n), _stream_handle(stream)), "sail_state_export")
+        return buf.raw[:n.value]
+
+    def state_import(self, blob: bytes, stream=None) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().sail_state_import(self._h, buf, len(blob), _stream_handle(stream)), "sail_state_import")
 
     def layout(self) -> tuple[int, int]:
         a, b = ctypes.c_int(), ctypes.c_int()

@@ -284,3 +284,29 @@ def test_fp32_anneal_quality_against_fp64(S):
     assert np.max(np.abs(a32.sum(axis=1) - A)) <= 1e-12 * A
     assert np.max(np.abs((a32 * wl.omega).sum(axis=1) - B)) <= 1e-12 * B
     assert np.sum(np.abs(s32 - s64)) * dw < 0.5
+
+
+def test_checkpoint_resume_is_bit_exact(S):
+    """Export after 250 sweeps, destroy, import into a fresh problem and
+    continue: identical bits to the uninterrupted run (counter-based stream)."""
+    wl = W.config1()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    ref = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    ref.init_walkers(64, wl.seed)
+    ref.run(S.Schedule(T), 0, 500)
+    a = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    a.init_walkers(64, wl.seed)
+    a.run(S.Schedule(T), 0, 250)
+    blob = a.state_export()
+    a.close()
+    b = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    b.init_walkers(64, 999)
+    b.state_import(blob)
+    b.run(S.Schedule(T), 250, 250)
+    assert np.array_equal(ref.read_chi2(), b.read_chi2())
+    ra, rb = ref.read_state(), b.read_state()
+    assert np.array_equal(ra["a"], rb["a"]) and np.array_equal(ra["F"], rb["F"])
+    with pytest.raises(S.SailError):
+        c = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        c.init_walkers(32, 1)
+        c.state_import(blob)
