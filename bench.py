@@ -38,10 +38,29 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=["c2", "c3"],
                     help="c2: FP64 loop (default); c3: FP32 loop with FP64 resync every 50 sweeps")
-    ap.add_argument("--cpu-sample-walkers", type=int, default=1024)
+    ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
+
+
+def measured_traffic(config: str):
+    """HBM bytes per sweep launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, if it was taken on the kernel source as it stands (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_sweep_{config}_traffic.md")
+    src = os.path.join(ROOT, "paper_1609_07936_amd", "csrc", "sail.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "|", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("source_sha256_16") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(wl, T, n_walkers, n_sweeps) -> dict:
@@ -49,13 +68,15 @@ def cpu_baseline(wl, T, n_walkers, n_sweeps) -> dict:
     op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     stride = max(1, wl.n_walkers // n_walkers)
     ids = np.arange(0, wl.n_walkers, stride)[:n_walkers]
-    an = O.Anneal(op, O.Schedule(T), wl.n_walkers, wl.seed, walker_ids=ids)
+    # sweeps only: the sample's walkers are a subset, so no resync or branching
+    an = O.Anneal(op, O.Schedule(T, branch_every=10 ** 6, resync_every=10 ** 6), wl.n_walkers, wl.seed,
+                  walker_ids=ids)
     t0 = time.perf_counter()
     out = an.run(0, n_sweeps)
     dt = time.perf_counter() - t0
     return {"value": out["proposals"] / dt, "unit": "proposals/s", "cores": O.max_threads(), "kind": "oracle",
             "sample": f"{ids.size} of {wl.n_walkers} walkers (every {stride}th), sweeps 0-{n_sweeps - 1} of the same "
-                      f"schedule, no branching: {out['proposals']} proposals in {dt:.2f} s"}
+                      f"schedule (sweeps only, no resync or branching): {out['proposals']} proposals in {dt:.2f} s"}
 
 
 def main():
@@ -139,7 +160,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(args.config),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": avg_ms,
             "launches": launches,
             "sweep_share_of_step": sweep_ms / (elapsed * 1e3),
