@@ -36,8 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed blocks of 100 sweeps (200 = the whole anneal)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3"],
-                    help="c2: FP64 loop (default); c3: FP32 loop with FP64 resync every 50 sweeps")
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2: FP64 loop (default); c3: FP32 loop with FP64 resync every 50 sweeps; "
+                         "c4: 256 mixed-size FP32 jobs in shared launches (a step is one round of 50 sweeps)")
+    ap.add_argument("--jobs", type=int, default=256, help="c4: number of jobs")
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,12 +81,126 @@ def cpu_baseline(wl, T, n_walkers, n_sweeps) -> dict:
                       f"schedule (sweeps only, no resync or branching): {out['proposals']} proposals in {dt:.2f} s"}
 
 
+def batched(args):
+    """Config 4: 256 independent inversions of mixed sizes (N_omega in
+    {128..1024}, N_tau in {32..256}, walkers in {256, 1024, 4096}), FP32 loop
+    with FP64 resync every 50 sweeps, 1000 sweeps each, branching every 100;
+    every round is one shared sweep launch plus shared resync / branch
+    launches.  A step is one round (50 sweeps of every job)."""
+    import torch
+    from paper_1609_07936_amd import sail as S
+    from paper_1609_07936_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    jobs = W.batch_jobs(args.jobs)
+    per_step = jobs[0].resync_every
+    n_sweeps = jobs[0].n_sweeps
+    steps = args.steps if args.steps * per_step <= n_sweeps else n_sweeps // per_step
+    warm = args.warmup
+    stream = torch.cuda.current_stream()
+    probs, scheds = [], []
+    t_tune = time.perf_counter()
+    for wl in jobs:
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.autotune_layout(wl.n_walkers, S.SAIL_FP32, stream=stream)
+        probs.append(gp)
+        scheds.append(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), branch_every=wl.branch_every,
+                                 resync_every=wl.resync_every))
+    t_tune = time.perf_counter() - t_tune
+    batch = S.Batch(probs)
+
+    def init():
+        for gp, wl in zip(probs, jobs):
+            gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP32, stream=stream)
+
+    init()
+    for s in range(warm):
+        batch.run(scheds, s * per_step, per_step, stream=stream)
+    init()
+    batch.run(scheds, 0, 0, stream=stream)  # uploads the schedules outside the timed region
+    batch.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        batch.run(scheds, s * per_step, per_step, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sweep_ms, launches = batch.sweep_timing(reset=True)
+    swept = steps * per_step
+    proposals = sum(wl.n_walkers * wl.omega.size for wl in jobs) * swept
+    flops = 8.0 * sum(wl.n_walkers * wl.omega.size * wl.tau.size for wl in jobs) * swept
+    achieved = flops / (sweep_ms * 1e-3) / 1e12
+    rel = np.array([np.median(gp.read_chi2(stream=stream)) / gp.chi2_unit for gp in probs])
+    layouts = {}
+    for gp in probs:
+        k = "x".join(map(str, gp.layout()))
+        layouts[k] = layouts.get(k, 0) + 1
+    line = {
+        "metric": "walker proposals/s at matched final chi2",
+        "value": proposals / elapsed,
+        "unit": "proposals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{len(jobs)} independent inversions in shared launches: N_omega in {{128,256,512,1024}} on "
+                        "[0,20], N_tau in {32,64,128,256} on [0.02,3], walkers in {256,1024,4096}, 2-3 seeded "
+                        "Lorentzians, noise log-uniform in [1e-6,1e-3] F, FP32 loop with FP64 resync every 50 "
+                        "sweeps, T 1e3->1e-2 (x chi2_0) over 1000 sweeps, imprinted branching every 100",
+            "n_jobs": len(jobs), "sweeps_timed": swept, "precision": "fp32 loop",
+            "layouts_lanes_x_tau_per_lane": layouts,
+        },
+        "jobs_per_s": len(jobs) * swept / n_sweeps / elapsed,
+        "quality": {
+            "final_chi2_over_chi2_0_median_over_jobs": float(np.median(rel)),
+            "final_chi2_over_chi2_0_max_over_jobs": float(rel.max()),
+            "at_sweep": swept,
+        },
+        "roofline": {
+            "kernel": "k_sweep_batched<float>",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": measured_traffic(args.config),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "avg_launch_ms": sweep_ms / launches,
+            "launches": launches,
+            "sweep_share_of_step": sweep_ms / (elapsed * 1e3),
+        },
+        "autotune_s": t_tune,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on the first four jobs, a walker sample of each, 400 sweeps
+        tot_p, tot_t = 0, 0.0
+        for wl in jobs[:4]:
+            T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+            cb = cpu_baseline(wl, T, min(512, wl.n_walkers), 400)
+            n_prop = min(512, wl.n_walkers) * wl.omega.size * 400
+            tot_p += n_prop
+            tot_t += n_prop / cb["value"]
+        line["cpu_baseline"] = {"value": tot_p / tot_t, "unit": "proposals/s", "cores": cb["cores"], "kind": "oracle",
+                                "sample": f"first 4 jobs, up to 512 walkers each (evenly strided), sweeps 0-399, "
+                                          f"sweeps only: {tot_p} proposals in {tot_t:.2f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the anneal runs on one device)",
               file=sys.stderr)
         sys.exit(2)
+    if args.config == "c4":
+        return batched(args)
     import torch
     from paper_1609_07936_amd import sail as S
     from paper_1609_07936_amd import workloads as W

@@ -171,11 +171,54 @@ sail_status sail_sweep_timing(sail_problem_t p, double *total_ms, int64_t *launc
 sail_status sail_state_export(sail_problem_t p, void *buf, size_t *bytes, void *stream);
 sail_status sail_state_import(sail_problem_t p, const void *buf, size_t bytes, void *stream);
 
-/* Device bytes a problem of this size holds (tables plus walker state). */
+/* Batches: many independent problems annealed together on one device
+ * (Sec. 2.5 and 3 per problem; the batch is a throughput device of this
+ * library, not of the paper).  The batch refers to the problems; it does not
+ * own them, and they must outlive it.  All problems live on one device and
+ * each appears once.
+ *
+ * sail_batch_run runs, for every problem i, global sweeps
+ * [first_sweep[i], first_sweep[i] + n_sweeps[i]) of *scheds[i] (host arrays of
+ * n_problems entries), with exactly the semantics and the random stream of
+ * sail_run_schedule on that problem alone: the results are bit-identical.
+ * The problems advance in rounds, each taking every unfinished problem to
+ * its next resync boundary in one shared sweep launch (per precision and
+ * lane layout), followed by shared launches of the resyncs, the branching
+ * solves and the imprints that fall due.  Problems may sit at different
+ * sweeps and have different sizes, walker counts, precisions and schedules.
+ * Traced sweeps (sail_set_trace) are refused.  Validation happens before any
+ * work is enqueued. */
+typedef struct sail_batch *sail_batch_t;
+sail_status sail_batch_create(const sail_problem_t *problems, int n_problems, sail_batch_t *out);
+void sail_batch_destroy(sail_batch_t b);
+sail_status sail_batch_run(sail_batch_t b, const sail_schedule *const *scheds, const int *first_sweep,
+                           const int *n_sweeps, void *stream);
+/* Timing of the shared sweep launches, as sail_set_timing / sail_sweep_timing. */
+sail_status sail_batch_set_timing(sail_batch_t b, int enable);
+sail_status sail_batch_sweep_timing(sail_batch_t b, double *total_ms, int64_t *launches, int reset);
+
+/* Upper bound of the device bytes a problem of this size holds at this
+ * precision (tables plus walker state, any lane layout), excluding the
+ * temperature schedule (8 bytes per sweep) and event logs beyond 64 events. */
 size_t sail_footprint_bytes(int n_omega, int n_tau, int n_walkers, int precision);
 
 /* Lanes per walker and tau points per lane the sweep kernel uses. */
 sail_status sail_layout(sail_problem_t p, int *lanes_per_walker, int *tau_per_lane);
+
+/* Requests tau points per lane for the next sail_walkers_init: 8 or 16 for
+ * FP64, 16 or 32 for FP32, 0 for the library's choice (16 FP64, 32 FP32).  A
+ * request the precision does not take falls back to the choice.  The walkers
+ * per wavefront follow as 64 / next_pow2(ceil(n_tau / tau_per_lane)).  The
+ * layout changes only the summation order of the residue change. */
+sail_status sail_set_tau_per_lane(sail_problem_t p, int tau_per_lane);
+
+/* Chooses the tau points per lane for this problem at n_walkers walkers and
+ * `precision` by timing a few sweeps of each candidate layout on `stream`,
+ * and requests it as sail_set_tau_per_lane does (*tau_per_lane receives it,
+ * may be NULL).  Results are cached per (n_omega, n_tau, n_walkers,
+ * precision) for the life of the process.  Leaves the problem without
+ * walkers: call it before sail_walkers_init. */
+sail_status sail_autotune_layout(sail_problem_t p, int n_walkers, int precision, int *tau_per_lane, void *stream);
 
 const char *sail_status_string(int status);
 const char *sail_last_error(void);

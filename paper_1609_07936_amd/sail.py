@@ -86,6 +86,20 @@ def lib() -> ctypes.CDLL:
     L.sail_state_export.restype = st
     L.sail_state_import.argtypes = [P, P, ctypes.c_size_t, P]
     L.sail_state_import.restype = st
+    L.sail_set_tau_per_lane.argtypes = [P, I]
+    L.sail_set_tau_per_lane.restype = st
+    L.sail_autotune_layout.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_int), P]
+    L.sail_autotune_layout.restype = st
+    L.sail_batch_create.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(P)]
+    L.sail_batch_create.restype = st
+    L.sail_batch_destroy.argtypes = [P]
+    L.sail_batch_destroy.restype = None
+    L.sail_batch_run.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ScheduleC)), P, P, P]
+    L.sail_batch_run.restype = st
+    L.sail_batch_set_timing.argtypes = [P, I]
+    L.sail_batch_set_timing.restype = st
+    L.sail_batch_sweep_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), I]
+    L.sail_batch_sweep_timing.restype = st
     L.sail_status_string.argtypes = [I]
     L.sail_status_string.restype = ctypes.c_char_p
     L.sail_last_error.argtypes = []
@@ -254,7 +268,65 @@ class Problem:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(lib().sail_state_import(self._h, buf, len(blob), _stream_handle(stream)), "sail_state_import")
 
+    def set_tau_per_lane(self, tpl: int) -> None:
+        _check(lib().sail_set_tau_per_lane(self._h, int(tpl)), "sail_set_tau_per_lane")
+
+    def autotune_layout(self, n_walkers: int, precision: int = SAIL_FP64, stream=None) -> int:
+        """Times the candidate lane layouts and requests the fastest for the
+        next init_walkers (this leaves the problem without walkers)."""
+        v = ctypes.c_int()
+        _check(lib().sail_autotune_layout(self._h, int(n_walkers), int(precision), ctypes.byref(v),
+                                          _stream_handle(stream)), "sail_autotune_layout")
+        self.n_walkers = 0
+        return v.value
+
     def layout(self) -> tuple[int, int]:
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(lib().sail_layout(self._h, ctypes.byref(a), ctypes.byref(b)), "sail_layout")
         return a.value, b.value
+
+
+class Batch:
+    """Many problems annealed together (see sail_batch_create); the batch
+    refers to the problems, which must stay alive while it is used."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (ctypes.c_void_p * len(self.problems))(*[pr._h for pr in self.problems])
+        h = ctypes.c_void_p()
+        _check(lib().sail_batch_create(arr, len(self.problems), ctypes.byref(h)), "sail_batch_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().sail_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, scheds, first_sweeps, n_sweeps, stream=None) -> None:
+        """scheds: one Schedule per problem (or one for all); first_sweeps and
+        n_sweeps: ints or one per problem."""
+        n = len(self.problems)
+        if isinstance(scheds, Schedule):
+            scheds = [scheds] * n
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(first_sweeps, dtype=np.int32), (n,)))
+        k = np.ascontiguousarray(np.broadcast_to(np.asarray(n_sweeps, dtype=np.int32), (n,)))
+        if len(scheds) != n:
+            raise ValueError("one schedule per problem")
+        ptrs = (ctypes.POINTER(ScheduleC) * n)(*[ctypes.pointer(sc.c) for sc in scheds])
+        _check(lib().sail_batch_run(self._h, ptrs, _p(f), _p(k), _stream_handle(stream)), "sail_batch_run")
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib().sail_batch_set_timing(self._h, int(bool(enable))), "sail_batch_set_timing")
+
+    def sweep_timing(self, reset: bool = False) -> tuple[float, int]:
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().sail_batch_sweep_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(bool(reset))),
+               "sail_batch_sweep_timing")
+        return ms.value, n.value

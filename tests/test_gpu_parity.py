@@ -184,20 +184,22 @@ def test_config2_full_size_branching_event(S):
     np.testing.assert_array_equal(st_post["a"][keep], st_pre["a"][keep])
 
 
-def test_deterministic_and_stageable(S):
-    """Two identical runs give identical bits, and a run split in stages
-    equals the run in one call."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deterministic_and_stageable(S, precision):
+    """Two identical runs give identical bits, and a run split in stages at
+    sweeps that are no resync boundary equals the run in one call (the state
+    a launch leaves behind is all the next one needs)."""
     wl = W.config1()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     res = []
-    for stages in ([(0, 400)], [(0, 400)], [(0, 37), (37, 163), (163, 400)]):
+    for stages in ([(0, 370)], [(0, 370)], [(0, 37), (37, 163), (163, 370)]):
         gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
-        gp.init_walkers(64, wl.seed)
+        gp.init_walkers(64, wl.seed, precision=precision)
         sched = S.Schedule(T)
         for k0, k1 in stages:
             gp.run(sched, k0, k1 - k0)
         st = gp.read_state()
-        res.append((gp.read_chi2(), st["a"], st["F"]))
+        res.append((gp.read_chi2(), st["a"], st["F"], st["rate"]))
     for r in res[1:]:
         for x, y in zip(res[0], r):
             assert np.array_equal(x, y)
