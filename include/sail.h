@@ -43,7 +43,9 @@ typedef enum {
     SAIL_ENOMEM = 3,      /* device or host allocation failed */
     SAIL_EDEVICE = 4,     /* a HIP runtime call failed */
     SAIL_ENUMERIC = 5,    /* a non-finite residue was found */
-    SAIL_ESTATE = 6       /* call out of order (e.g. run before init) */
+    SAIL_ESTATE = 6,      /* call out of order (e.g. run before init) */
+    SAIL_ETIMEOUT = 7,    /* a wait ended before its job did */
+    SAIL_ECANCELLED = 8   /* the server shut down before the job finished */
 } sail_status;
 
 typedef enum {
@@ -196,6 +198,78 @@ sail_status sail_batch_run(sail_batch_t b, const sail_schedule *const *scheds, c
 /* Timing of the shared sweep launches, as sail_set_timing / sail_sweep_timing. */
 sail_status sail_batch_set_timing(sail_batch_t b, int enable);
 sail_status sail_batch_sweep_timing(sail_batch_t b, double *total_ms, int64_t *launches, int reset);
+
+/* Served anneals: a server owns one device, a device arena of hbm_bytes and
+ * a host thread.  Submitted jobs queue in arrival order; the head job is
+ * admitted when at most max_jobs - 1 jobs are in flight and its footprint
+ * (its tables, walker state, schedule and outputs) fits in the free part of
+ * the arena, so the device memory of all in-flight jobs never exceeds
+ * hbm_bytes and no device allocation happens per job.  Admitted jobs keep all
+ * state on the device and advance together in the rounds of sail_batch_run:
+ * every round one shared sweep launch takes each in-flight job, whatever its
+ * stage, to its next resync boundary, and jobs join or leave between rounds
+ * (continuous batching).  A job runs its whole schedule (sweeps [0, n_T)) from
+ * sail_walkers_init, with the semantics and random stream of
+ * sail_run_schedule: its outputs are bit-identical to the same job run alone.
+ * Times are seconds on the server's monotonic clock (sail_server_clock). */
+typedef struct sail_server *sail_server_t;
+
+typedef struct {
+    int device;
+    size_t hbm_bytes; /* device arena; admission budget of all in-flight jobs */
+    int max_jobs;     /* in-flight jobs at most */
+} sail_server_config;
+
+typedef struct {
+    /* the problem, as sail_problem_create (host arrays, copied at submit) */
+    const double *omega; int n_omega;
+    const double *tau; int n_tau;
+    const double *F; const double *sigma;
+    double m0, m1;
+    int kernel_mode;
+    /* the walkers, as sail_walkers_init */
+    int n_walkers;
+    uint64_t seed;
+    int precision;
+    int tau_per_lane;      /* as sail_set_tau_per_lane; -1: sail_autotune_layout */
+    sail_schedule sched;   /* T copied at submit; all n_T sweeps run */
+} sail_job;
+
+typedef struct {
+    int status;                       /* sail_status of the job */
+    double t_submit, t_admit, t_done; /* server clock */
+    double chi2_unit;                 /* starting residue chi^2_0 */
+    double chi2_min, chi2_median;     /* final residues over the walkers */
+    int n_omega, n_walkers;
+} sail_job_result;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed;
+    int queued, in_flight;
+    size_t arena_bytes, arena_used, arena_peak;
+    int64_t rounds;
+    double sweep_ms; /* summed duration of the shared sweep launches */
+    int64_t sweep_launches;
+} sail_server_stats;
+
+/* Starts the server thread.  SAIL_ENOMEM if the arena cannot be allocated. */
+sail_status sail_server_create(const sail_server_config *cfg, sail_server_t *out);
+/* Queues a job (thread-safe); inputs are validated as by sail_problem_create /
+ * sail_run_schedule where that needs no device (the rest is reported in the
+ * job's result).  SAIL_EINVAL if the job could never fit the arena. */
+sail_status sail_server_submit(sail_server_t s, const sail_job *job, int64_t *id);
+/* Waits up to timeout_s seconds (< 0: no limit) for job `id`; on SAIL_OK fills
+ * *res and, if mean_spectrum (host, n_omega doubles) is not NULL, the
+ * ensemble-mean spectrum, and forgets the job.  SAIL_ETIMEOUT leaves it. */
+sail_status sail_server_wait(sail_server_t s, int64_t id, double timeout_s, sail_job_result *res,
+                             double *mean_spectrum);
+sail_status sail_server_get_stats(sail_server_t s, sail_server_stats *out);
+double sail_server_clock(sail_server_t s);
+/* Arena bytes a job takes while in flight (0 for a malformed job). */
+size_t sail_job_footprint_bytes(const sail_job *job);
+/* Stops the thread: queued and in-flight jobs end with SAIL_ECANCELLED (after
+ * the device has finished their work), then frees everything. */
+void sail_server_destroy(sail_server_t s);
 
 /* Upper bound of the device bytes a problem of this size holds at this
  * precision (tables plus walker state, any lane layout), excluding the

@@ -36,6 +36,41 @@ class ScheduleC(ctypes.Structure):
     ]
 
 
+class JobC(ctypes.Structure):
+    _fields_ = [
+        ("omega", ctypes.c_void_p), ("n_omega", ctypes.c_int),
+        ("tau", ctypes.c_void_p), ("n_tau", ctypes.c_int),
+        ("F", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+        ("m0", ctypes.c_double), ("m1", ctypes.c_double),
+        ("kernel_mode", ctypes.c_int),
+        ("n_walkers", ctypes.c_int), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int),
+        ("tau_per_lane", ctypes.c_int),
+        ("sched", ScheduleC),
+    ]
+
+
+class ServerConfigC(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hbm_bytes", ctypes.c_size_t), ("max_jobs", ctypes.c_int)]
+
+
+class JobResultC(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+        ("chi2_unit", ctypes.c_double), ("chi2_min", ctypes.c_double), ("chi2_median", ctypes.c_double),
+        ("n_omega", ctypes.c_int), ("n_walkers", ctypes.c_int),
+    ]
+
+
+class ServerStatsC(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64), ("queued", ctypes.c_int), ("in_flight", ctypes.c_int),
+        ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+        ("rounds", ctypes.c_int64), ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -100,6 +135,20 @@ def lib() -> ctypes.CDLL:
     L.sail_batch_set_timing.restype = st
     L.sail_batch_sweep_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), I]
     L.sail_batch_sweep_timing.restype = st
+    L.sail_server_create.argtypes = [ctypes.POINTER(ServerConfigC), ctypes.POINTER(P)]
+    L.sail_server_create.restype = st
+    L.sail_server_submit.argtypes = [P, ctypes.POINTER(JobC), ctypes.POINTER(ctypes.c_int64)]
+    L.sail_server_submit.restype = st
+    L.sail_server_wait.argtypes = [P, ctypes.c_int64, D, ctypes.POINTER(JobResultC), P]
+    L.sail_server_wait.restype = st
+    L.sail_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStatsC)]
+    L.sail_server_get_stats.restype = st
+    L.sail_server_clock.argtypes = [P]
+    L.sail_server_clock.restype = D
+    L.sail_job_footprint_bytes.argtypes = [ctypes.POINTER(JobC)]
+    L.sail_job_footprint_bytes.restype = ctypes.c_size_t
+    L.sail_server_destroy.argtypes = [P]
+    L.sail_server_destroy.restype = None
     L.sail_status_string.argtypes = [I]
     L.sail_status_string.restype = ctypes.c_char_p
     L.sail_last_error.argtypes = []
@@ -330,3 +379,72 @@ class Batch:
         _check(lib().sail_batch_sweep_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(bool(reset))),
                "sail_batch_sweep_timing")
         return ms.value, n.value
+
+
+SAIL_ETIMEOUT, SAIL_ECANCELLED = 7, 8
+AUTOTUNE = -1
+
+
+class Server:
+    """A served-anneal server on one device (see sail_server_create): jobs
+    are submitted from any thread and waited for by id."""
+
+    def __init__(self, hbm_bytes: int, max_jobs: int, device: int = 0):
+        cfg = ServerConfigC(int(device), int(hbm_bytes), int(max_jobs))
+        h = ctypes.c_void_p()
+        _check(lib().sail_server_create(ctypes.byref(cfg), ctypes.byref(h)), "sail_server_create")
+        self._h = h
+        self._n_omega = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().sail_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _job(omega, tau, F, sigma, m0, m1, n_walkers, seed, sched, precision, tau_per_lane, mode):
+        om, ta, f = _f64(omega), _f64(tau), _f64(F)
+        sg = None if sigma is None else _f64(sigma)
+        job = JobC(_p(om), om.size, _p(ta), ta.size, _p(f), _p(sg), float(m0), float(m1), int(mode),
+                   int(n_walkers), int(seed), int(precision), int(tau_per_lane), sched.c)
+        return job, (om, ta, f, sg)
+
+    @staticmethod
+    def job_footprint(omega, tau, n_walkers, sched: Schedule, precision=SAIL_FP64) -> int:
+        om, ta = _f64(omega), _f64(tau)
+        job = JobC(_p(om), om.size, _p(ta), ta.size, _p(ta), None, 1.0, 0.0, 0, int(n_walkers), 0, int(precision),
+                   0, sched.c)
+        return int(lib().sail_job_footprint_bytes(ctypes.byref(job)))
+
+    def submit(self, omega, tau, F, sigma, m0, m1, n_walkers, seed, sched: Schedule, precision=SAIL_FP64,
+               tau_per_lane=AUTOTUNE, mode=SAIL_K_POINT) -> int:
+        job, keep = self._job(omega, tau, F, sigma, m0, m1, n_walkers, seed, sched, precision, tau_per_lane, mode)
+        om = keep[0]
+        jid = ctypes.c_int64()
+        _check(lib().sail_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid)), "sail_server_submit")
+        self._n_omega[jid.value] = om.size
+        return jid.value
+
+    def wait(self, job_id: int, timeout: float = -1.0) -> dict:
+        mean = np.zeros(max(1, self._n_omega.get(job_id, 0)))
+        r = JobResultC()
+        _check(lib().sail_server_wait(self._h, int(job_id), float(timeout), ctypes.byref(r), _p(mean)),
+               "sail_server_wait")
+        self._n_omega.pop(job_id, None)
+        out = {k: getattr(r, k) for k, _ in JobResultC._fields_}
+        out["mean_spectrum"] = mean if r.status == 0 else None
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStatsC()
+        _check(lib().sail_server_get_stats(self._h, ctypes.byref(st)), "sail_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStatsC._fields_}
+
+    def clock(self) -> float:
+        return float(lib().sail_server_clock(self._h))

@@ -1,0 +1,116 @@
+"""GPU: the served-anneal loop.
+
+A served job runs the batch rounds on its own device-resident state, so its
+outputs (ensemble-mean spectrum, final residues, starting residue) are
+bit-identical to the same job run alone through sail_run_schedule, which the
+parity tests check against the oracle.  Admission keeps the footprint of the
+in-flight jobs within the arena.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1609_07936_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1609_07936_amd import sail
+    sail.lib()
+    return sail
+
+
+def _sched(S, wl):
+    return S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), branch_every=wl.branch_every,
+                      resync_every=wl.resync_every)
+
+
+def _alone(S, wl, prec, tpl):
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    if tpl == S.AUTOTUNE:
+        gp.autotune_layout(wl.n_walkers, prec)
+    else:
+        gp.set_tau_per_lane(tpl)
+    gp.init_walkers(wl.n_walkers, wl.seed, precision=prec)
+    gp.run(_sched(S, wl), 0, wl.n_sweeps)
+    chi2 = gp.read_chi2()
+    return {"mean": gp.read_spectrum(), "chi2_unit": gp.chi2_unit, "chi2_min": chi2.min(),
+            "chi2_median": float(np.median(chi2))}
+
+
+def test_served_jobs_match_alone(S):
+    """Eight jobs of mixed sizes and precisions arrive in two waves while the
+    first wave runs; every result equals the job run alone, bit for bit."""
+    jobs = W.batch_jobs(8, base_seed=3000, n_sweeps=200)
+    cfg = [(S.SAIL_FP32, S.AUTOTUNE), (S.SAIL_FP64, 16), (S.SAIL_FP32, 16), (S.SAIL_FP64, S.AUTOTUNE),
+           (S.SAIL_FP32, 32), (S.SAIL_FP64, 8), (S.SAIL_FP32, S.AUTOTUNE), (S.SAIL_FP64, 16)]
+    srv = S.Server(hbm_bytes=4 << 30, max_jobs=16)
+    ids = []
+    for i, (wl, (prec, tpl)) in enumerate(zip(jobs, cfg)):
+        if i == 4:
+            time.sleep(0.2)  # the second wave joins jobs already in flight
+        ids.append(srv.submit(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1, wl.n_walkers, wl.seed, _sched(S, wl),
+                              precision=prec, tau_per_lane=tpl))
+    res = [srv.wait(j, timeout=120.0) for j in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 8 and st["failed"] == 0 and st["rounds"] > 0
+    for r, wl, (prec, tpl) in zip(res, jobs, cfg):
+        assert r["status"] == 0, r
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+        ref = _alone(S, wl, prec, tpl)
+        tag = f"{wl.name} {wl.omega.size}x{wl.tau.size} {wl.n_walkers} prec {prec} tpl {tpl}"
+        np.testing.assert_array_equal(r["mean_spectrum"], ref["mean"], err_msg=tag)
+        for k in ("chi2_unit", "chi2_min", "chi2_median"):
+            assert r[k] == ref[k], (tag, k, r[k], ref[k])
+
+
+def test_server_admission_within_budget(S):
+    """An arena the size of the two largest jobs: six jobs all complete, the
+    footprints in flight never exceed the arena, and a job larger than the
+    arena is refused at submission."""
+    jobs = W.batch_jobs(6, base_seed=4000, n_sweeps=100)
+    scheds = [_sched(S, wl) for wl in jobs]
+    foot = [S.Server.job_footprint(wl.omega, wl.tau, wl.n_walkers, sc, S.SAIL_FP32) for wl, sc in zip(jobs, scheds)]
+    budget = sum(sorted(foot)[-2:])
+    srv = S.Server(hbm_bytes=budget, max_jobs=8)
+    big = next(j for j in W.batch_jobs(64, base_seed=4000, n_sweeps=100) if j.omega.size == 1024)
+    assert S.Server.job_footprint(big.omega, big.tau, 16384, scheds[0], S.SAIL_FP32) > budget
+    with pytest.raises(S.SailError):
+        srv.submit(big.omega, big.tau, big.Ft, big.sigma, big.m0, big.m1, 16384, 1, scheds[0], precision=S.SAIL_FP32)
+    ids = [srv.submit(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1, wl.n_walkers, wl.seed, sc,
+                      precision=S.SAIL_FP32, tau_per_lane=16) for wl, sc in zip(jobs, scheds)]
+    res = [srv.wait(j, timeout=120.0) for j in ids]
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    assert st["arena_peak"] <= st["arena_bytes"]
+    # the footprints of the jobs in flight never exceed the arena
+    events = sorted([(r["t_admit"], f) for r, f in zip(res, foot)] + [(r["t_done"], -f) for r, f in zip(res, foot)],
+                    key=lambda e: (e[0], e[1]))
+    held = np.cumsum([e[1] for e in events])
+    assert held.max() <= st["arena_bytes"]
+    assert held.max() < sum(foot)  # admission did hold jobs back
+
+
+def test_server_timeout_and_shutdown(S):
+    """A wait shorter than the job returns a timeout and leaves the job; the
+    server shuts down with jobs queued and in flight."""
+    wl = W.batch_jobs(1, base_seed=5000, n_sweeps=1000)[0]
+    sc = _sched(S, wl)
+    srv = S.Server(hbm_bytes=1 << 30, max_jobs=2)
+    ids = [srv.submit(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1, wl.n_walkers, wl.seed + i, sc,
+                      precision=S.SAIL_FP32, tau_per_lane=16) for i in range(6)]
+    with pytest.raises(S.SailError) as e:
+        srv.wait(ids[-1], timeout=0.01)
+    assert e.value.status == S.SAIL_ETIMEOUT
+    with pytest.raises(S.SailError):
+        srv.wait(10 ** 9, timeout=0.01)
+    t0 = time.perf_counter()
+    srv.close()
+    assert time.perf_counter() - t0 < 60
