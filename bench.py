@@ -36,9 +36,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed blocks of 100 sweeps (200 = the whole anneal)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: FP64 loop (default); c3: FP32 loop with FP64 resync every 50 sweeps; "
-                         "c4: 256 mixed-size FP32 jobs in shared launches (a step is one round of 50 sweeps)")
+                         "c4: 256 mixed-size FP32 jobs in shared launches (a step is one round of 50 sweeps); "
+                         "c5: Poisson stream of c4-distributed jobs into the server")
+    ap.add_argument("--rate", type=float, default=50.0, help="c5: offered load, jobs/s")
+    ap.add_argument("--duration", type=float, default=30.0, help="c5: arrival window, s")
+    ap.add_argument("--max-jobs", type=int, default=256, help="c5: in-flight jobs at most")
     ap.add_argument("--jobs", type=int, default=256, help="c4: number of jobs")
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
@@ -193,6 +197,111 @@ def batched(args):
     print(json.dumps(line), flush=True)
 
 
+def served(args):
+    """Config 5: jobs from config 4's distribution (1000 sweeps each) arrive
+    as a Poisson stream into the server; reports completed solves/s over the
+    whole run and the submit-to-result latency percentiles, with sequential
+    solo solves of the first jobs as the comparison."""
+    import threading
+    import torch
+    from paper_1609_07936_amd import sail as S
+    from paper_1609_07936_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(5)  # arrival seed
+    n_jobs = max(1, int(rng.poisson(args.rate * args.duration)))
+    arrivals = np.sort(rng.uniform(0.0, args.duration, n_jobs))
+    jobs = W.batch_jobs(n_jobs, base_seed=20000)
+    scheds = [S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), branch_every=wl.branch_every,
+                         resync_every=wl.resync_every) for wl in jobs]
+    # layouts of every shape tuned before the clock starts
+    shapes = {}
+    for wl in jobs:
+        shapes.setdefault((wl.omega.size, wl.tau.size, wl.n_walkers), wl)
+    for wl in shapes.values():
+        S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1).autotune_layout(wl.n_walkers, S.SAIL_FP32)
+    # sequential solo solves of the first jobs
+    solo = []
+    for wl, sc in list(zip(jobs, scheds))[:3]:
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.autotune_layout(wl.n_walkers, S.SAIL_FP32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP32)
+        gp.run(sc, 0, wl.n_sweeps)
+        gp.read_chi2()
+        solo.append(time.perf_counter() - t0)
+    srv = S.Server(hbm_bytes=64 << 30, max_jobs=args.max_jobs)
+    ids = [None] * n_jobs
+    t_base = srv.clock()
+
+    def submitter():
+        for i, (wl, sc) in enumerate(zip(jobs, scheds)):
+            dt = t_base + arrivals[i] - srv.clock()
+            if dt > 0:
+                time.sleep(dt)
+            ids[i] = srv.submit(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1, wl.n_walkers, wl.seed, sc,
+                                precision=S.SAIL_FP32)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    res = []
+    for i in range(n_jobs):
+        while ids[i] is None:
+            time.sleep(0.001)
+        res.append(srv.wait(ids[i]))
+        if i % 200 == 0:
+            print(f"served {i + 1}/{n_jobs} at {srv.clock() - t_base:.1f} s", file=sys.stderr, flush=True)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    ok = [r for r in res if r["status"] == 0]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in ok])
+    wait = np.array([r["t_admit"] - r["t_submit"] for r in ok])
+    span = max(r["t_done"] for r in ok) - t_base
+    prop = sum(wl.n_walkers * wl.omega.size * wl.n_sweeps for wl, r in zip(jobs, res) if r["status"] == 0)
+    flops = 8.0 * sum(wl.n_walkers * wl.omega.size * wl.tau.size * wl.n_sweeps for wl, r in zip(jobs, res)
+                      if r["status"] == 0)
+    rel = np.array([r["chi2_median"] / r["chi2_unit"] for r in ok])
+    achieved = flops / (st["sweep_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "solves/s with p50/p99 latency at matched final chi2",
+        "value": len(ok) / span,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(ok),
+        "warmup": 0,
+        "ms_per_step": span / max(1, len(ok)) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Poisson arrivals at {args.rate:g} jobs/s for {args.duration:g} s of config-4 distributed "
+                        "jobs (N_omega in {128..1024}, N_tau in {32..256}, walkers in {256,1024,4096}, 1000 "
+                        "sweeps, FP32 loop, FP64 resync every 50, branching every 100) into one server "
+                        f"(64 GiB arena, at most {args.max_jobs} in flight)",
+            "offered_jobs": n_jobs, "rate": args.rate, "duration_s": args.duration,
+        },
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max()), "queue_wait_p50": float(np.percentile(wait, 50)),
+                      "queue_wait_p99": float(np.percentile(wait, 99))},
+        "proposals_per_s": prop / span,
+        "sequential_solo_solve_s": solo,
+        "sequential_solves_per_s": len(solo) / sum(solo),
+        "failed": len(res) - len(ok),
+        "quality": {"final_chi2_over_chi2_0_median_over_jobs": float(np.median(rel))},
+        "roofline": {"kernel": "k_sweep_batched<float>", "bound": "alu", "achieved": achieved,
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": None, "avg_launch_ms": st["sweep_ms"] / max(1, st["sweep_launches"]),
+                     "launches": st["sweep_launches"]},
+        "server": st,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -201,6 +310,8 @@ def main():
         sys.exit(2)
     if args.config == "c4":
         return batched(args)
+    if args.config == "c5":
+        return served(args)
     import torch
     from paper_1609_07936_amd import sail as S
     from paper_1609_07936_amd import workloads as W
