@@ -280,7 +280,7 @@ size_t sail_footprint_bytes(int n_omega, int n_tau, int n_walkers, int precision
 sail_status sail_layout(sail_problem_t p, int *lanes_per_walker, int *tau_per_lane);
 
 /* Requests tau points per lane for the next sail_walkers_init: 8 or 16 for
- * FP64, 16 or 32 for FP32, 0 for the library's choice (16 FP64, 32 FP32).  A
+ * FP64, 16 or 32 for FP32, 0 for the library's choice (16).  A
  * request the precision does not take falls back to the choice.  The walkers
  * per wavefront follow as 64 / next_pow2(ceil(n_tau / tau_per_lane)).  The
  * layout changes only the summation order of the residue change. */

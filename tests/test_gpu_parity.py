@@ -240,18 +240,21 @@ def test_errors_leave_problem_usable(S):
     assert np.all(np.isfinite(gp.read_chi2()))
 
 
-def test_fp32_loop_first_sweeps_within_fp32_bar(S):
+@pytest.mark.parametrize("tau_per_lane", [16, 32])
+def test_fp32_loop_first_sweeps_within_fp32_bar(S, tau_per_lane):
     """FP32 residual loop (config 3's variant): every proposal of the first two
-    sweeps against the FP64 oracle.  The loop carries Phi, G and the columns
-    in FP32, so the bar is (TPL + log2 L + 8) u_32 M <= 1e-5 M; decisions whose
-    margin falls inside that band are adopted by the oracle."""
+    sweeps against the FP64 oracle, in both FP32 lane layouts.  The loop
+    carries Phi, G and the columns in FP32, so the bar is
+    (TPL + log2 L + 8) u_32 M <= 1e-5 M; decisions whose margin falls inside
+    that band are adopted by the oracle."""
     import torch
     wl = W.config1()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.set_tau_per_lane(tau_per_lane)
     gp.init_walkers(64, wl.seed, precision=S.SAIL_FP32)
     lanes, tpl = gp.layout()
-    assert tpl == 32
+    assert tpl == tau_per_lane and lanes * tpl == 32
     ns = 2
     d, f = _trace_buffers(64, ns, wl.omega.size)
     gp.set_trace(0, ns, d.data_ptr(), f.data_ptr())
