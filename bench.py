@@ -50,12 +50,21 @@ def parse():
     return ap.parse_args()
 
 
+def sweep_source_digest() -> str:
+    """sha256 prefix of the sweep kernel's source: sail.hip from its start to
+    the end of k_sweep_batched (the helpers, the sweep and its wrappers)."""
+    import hashlib
+    text = open(os.path.join(ROOT, "paper_1609_07936_amd", "csrc", "sail.hip"), "rb").read()
+    i = text.index(b"void k_sweep_batched(")
+    j = text.index(b"\n}\n", i) + 3
+    return hashlib.sha256(text[:j]).hexdigest()[:16]
+
+
 def measured_traffic(config: str):
     """HBM bytes per sweep launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary, if it was taken on the kernel source as it stands (else None)."""
-    import hashlib
+    summary, if it was taken on the sweep kernel's source as it stands (else
+    None)."""
     path = os.path.join(ROOT, "profiles", f"k_sweep_{config}_traffic.md")
-    src = os.path.join(ROOT, "paper_1609_07936_amd", "csrc", "sail.hip")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -63,8 +72,7 @@ def measured_traffic(config: str):
         if ":" in line and not line.startswith((" ", "|", "#")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if fields.get("source_sha256_16") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("sweep_source_sha256_16") != sweep_source_digest() or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
 

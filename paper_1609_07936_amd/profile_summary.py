@@ -22,8 +22,8 @@ def kernel_table(con) -> list[tuple]:
 def pmc_table(con, counters) -> list[tuple]:
     rows = []
     for cname in counters:
-        q = ("select kernel_name, count(*), avg(counter_value), sum(counter_value) from counters_collection "
-             "where counter_name = ? group by kernel_name order by sum(counter_value) desc")
+        q = ("select kernel_name, count(*), avg(value), sum(value) from counters_collection "
+             "where counter_name = ? group by kernel_name order by sum(value) desc")
         for r in con.execute(q, (cname,)):
             rows.append((cname,) + tuple(r))
     return rows
