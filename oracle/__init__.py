@@ -73,6 +73,7 @@ class AnnealArgs(ctypes.Structure):
         ("n_near_ties", ctypes.c_int64), ("n_hard_mismatch", ctypes.c_int64),
         ("n_proposals", ctypes.c_int64), ("n_accepted", ctypes.c_int64),
         ("first_mismatch", ctypes.c_int32 * 3),
+        ("trace_p", ctypes.c_void_p), ("trace_s", ctypes.c_void_p),
     ]
 
 
@@ -307,9 +308,12 @@ class Anneal:
             out["dchi2"] = np.zeros(shape)
             out["cond"] = np.zeros(shape)
             out["accept"] = np.zeros(shape, dtype=np.uint8)
+            out["p"] = np.zeros(shape, dtype=np.int32)
+            out["s"] = np.zeros(shape, dtype=np.int32)
             g.trace_k0, g.trace_k1 = tk0, tk1
             g.trace_dchi2, g.trace_cond = _p(out["dchi2"]), _p(out["cond"])
             g.trace_accept = _p(out["accept"])
+            g.trace_p, g.trace_s = _p(out["p"]), _p(out["s"])
             if replay is not None:
                 rep = np.ascontiguousarray(replay, dtype=np.uint8)
                 assert rep.shape == shape
@@ -321,6 +325,7 @@ class Anneal:
         else:
             g.trace_k0 = g.trace_k1 = 0
             g.trace_dchi2 = g.trace_cond = g.trace_accept = g.replay_accept = None
+            g.trace_p = g.trace_s = None
         g.n_near_ties = g.n_hard_mismatch = g.n_proposals = g.n_accepted = 0
         rc = lib().or_anneal(ctypes.byref(g), int(k0), int(k1), _p(self.a), _p(self.F), _p(self.chi2),
                              _p(self.rate))
@@ -332,6 +337,7 @@ class Anneal:
                    accepted=g.n_accepted, first_mismatch=tuple(g.first_mismatch))
         g.trace_k0 = g.trace_k1 = 0
         g.trace_dchi2 = g.trace_cond = g.trace_accept = g.replay_accept = None
+        g.trace_p = g.trace_s = None
         return out
 
     def mean_spectrum(self) -> np.ndarray:

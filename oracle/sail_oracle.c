@@ -370,6 +370,9 @@ typedef struct {
     /* results */
     int64_t n_near_ties, n_hard_mismatch, n_proposals, n_accepted;
     int32_t first_mismatch[3]; /* walker, sweep, proposal of the earliest hard mismatch, or -1 */
+    /* optional: the two bins each traced proposal chose (after the
+     * selection walk), same layout as the other traces */
+    int32_t *trace_p, *trace_s;
 } or_anneal_args;
 
 typedef struct { int64_t near, hard, props, acc; int32_t fk, fq; } walker_log;
@@ -462,6 +465,8 @@ static void walker_sweeps(const or_anneal_args *g, int l, int k0, int k1,
                     }
                 }
             }
+            if (traced && g->trace_p) g->trace_p[toff + q] = p;
+            if (traced && g->trace_s) g->trace_s[toff + q] = s;
             /* bit 0: accepted, bit 1: move admissible (p != s and a' >= 0) */
             if (traced && g->trace_accept) g->trace_accept[toff + q] = (uint8_t)(accept | (ok << 1));
             lg->props++;

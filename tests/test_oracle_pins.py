@@ -267,6 +267,40 @@ def test_first_proposal_dchi2_exact_rational():
         assert abs(got - exact) <= 1e-13 * M, (l, got, exact, M)
 
 
+@pytest.mark.parametrize("walk_len", [1, 3])
+def test_selection_walk_distribution_is_exact_markov_power(walk_len):
+    """Sec. 2.3 index selection: a walk of independence Metropolis steps
+    with uniform proposals, target a_j / A, started from a uniform index.
+    Over many walkers in their first proposal (spectrum known exactly), the
+    chosen p and s follow u P^L with P_ij = min(1, a_j / a_i) / N off the
+    diagonal, the brute-force distribution (chi-square goodness of fit)."""
+    No, Nt, n = 6, 4, 60000
+    omega = (np.arange(No) + 0.5) * 1.0
+    tau = np.linspace(0.1, 1.0, Nt)
+    a0 = np.array([5.0, 0.5, 2.0, 0.05, 1.0, 3.0])
+    K = np.exp(-np.outer(omega, tau)) / (2 * np.pi)
+    Ft = a0 @ K
+    m0, m1 = a0.sum(), (a0 * omega).sum()
+    prob = O.Problem(omega, tau, Ft, None, m0, m1)
+    sched = O.Schedule(np.ones(4), branch_every=10 ** 6, resync_every=10 ** 6, walk_len=walk_len)
+    an = O.Anneal(prob, sched, n, 11)
+    a_start = an.a[0].copy()
+    assert np.all(an.a == a_start)
+    out = an.run(0, 1, trace=(0, 1))
+    ratio = np.minimum(1.0, a_start[None, :] / a_start[:, None]) / No
+    P = ratio.copy()
+    np.fill_diagonal(P, 0.0)
+    np.fill_diagonal(P, 1.0 - P.sum(axis=1))
+    pi = np.full(No, 1.0 / No) @ np.linalg.matrix_power(P, walk_len)
+    for key in ("p", "s"):
+        counts = np.bincount(out[key][:, 0, 0], minlength=No)
+        expect = pi * n
+        stat = np.sum((counts - expect) ** 2 / expect)
+        assert stat < 25.0, (key, counts, expect)  # chi-square, 5 dof: P(> 25) < 2e-4
+    # the walk must matter: its law differs measurably from the uniform start
+    assert np.max(np.abs(pi - 1.0 / No)) > 0.02
+
+
 def test_zero_temperature_never_raises_chi2_and_infinite_accepts_all_admissible():
     wl, prob = _c1_problem()
     S = 20
