@@ -124,6 +124,24 @@ def test_edge_shapes_lockstep(S, case):
     _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma)
 
 
+@pytest.mark.parametrize("walk_len", [1, 4])
+def test_selection_walk_lockstep(S, walk_len):
+    """Sec. 2.3 index selection with a walk of independence Metropolis steps
+    on a_j / A: config 1, 64 walkers, 300 sweeps (three branching events),
+    every proposal traced against the oracle (a different chosen pair would
+    change the residue change far beyond the bar)."""
+    wl = W.config1()
+    _anneal_lockstep(S, wl, 64, wl.seed, 300, dict(walk_len=walk_len))
+
+
+def test_selection_walk_ragged_tail(S):
+    """The walk with a bin count that leaves a partial last batch (no-op
+    records past N_omega take no walk)."""
+    tgt = W.Target([1.2, 3.0], [0.3, 0.6], [0.5, 0.5], 6.0)
+    wl = W.make("rw", 6.0, 45, W.uniform_tau(0.05, 1.5, 19), tgt, 1e-4, 3, 21, 120, 1e2, 1e-3, 60, 30, 5)
+    _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, dict(branch_every=60, resync_every=30, walk_len=2))
+
+
 def test_config2_full_size_sampled_lockstep(S):
     """Config 2 at full size (16384 walkers, 512 bins, 128 times) in the
     launch configuration the benchmark times: three traced sweeps, checked on
