@@ -77,6 +77,41 @@ def measured_traffic(config: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream) -> dict:
+    """The FP32-loop anneal against the FP64 path (the FP64 GPU path is
+    parity-tested against the CPU oracle; the oracle itself would take hours
+    at this size): the same walkers, seeds and schedule with resync every 100
+    sweeps, run after the timed region.  Reports the L1 distance of the
+    averaged spectra (against a unit zeroth moment), the ratio of the median
+    final residues, the FP32 path's largest sum-rule drift over the walkers,
+    and its proposals/s against the FP64 path's."""
+    import torch
+    c2 = W.config2()
+    sp32 = gp32.read_spectrum(stream=stream)
+    a32 = gp32.read_state(stream=stream)["a"]
+    dw = wl.omega[1] - wl.omega[0]
+    A, B = wl.m0 / dw, wl.m1 / dw
+    drift = max(float(np.max(np.abs(a32.sum(axis=1) - A)) / A),
+                float(np.max(np.abs((a32 * wl.omega).sum(axis=1) - B)) / B))
+    del a32
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP64, stream=stream)
+    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=c2.resync_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(wl.n_sweeps // SWEEPS_PER_STEP):
+        gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sp64 = gp.read_spectrum(stream=stream)
+    chi2_64 = gp.read_chi2(stream=stream)
+    return {"spectrum_L1": float(np.sum(np.abs(sp32 - sp64)) * dw / wl.m0),
+            "median_chi2_ratio_fp32_over_fp64": float(np.median(chi2_32) / np.median(chi2_64)),
+            "sum_rule_drift_max_fp32": drift,
+            "fp64_proposals_per_s": wl.n_walkers * wl.omega.size * wl.n_sweeps / dt,
+            "speedup_fp32_over_fp64": value32 / (wl.n_walkers * wl.omega.size * wl.n_sweeps / dt)}
+
+
 def cpu_baseline(wl, T, n_walkers, n_sweeps) -> dict:
     import oracle as O
     op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
@@ -402,6 +437,8 @@ def main():
             "sweep_share_of_step": sweep_ms / (elapsed * 1e3),
         },
     }
+    if fp32 and steps * SWEEPS_PER_STEP == n_sweeps_total:
+        line["vs_fp64"] = fp64_comparison(S, W, wl, T, gp, chi2, value, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps)
     print(json.dumps(line), flush=True)
