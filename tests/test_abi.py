@@ -38,7 +38,8 @@ def test_host_only_entry_points(S):
     assert (sc.branch_every, sc.branch_fraction, sc.imprint_t, sc.amp_p, sc.amp_m) == (100, 0.25, 0.1, 1.0, 2)
     assert L.sail_status_string(0) == b"ok" and L.sail_status_string(2) == b"sum rules infeasible"
     fb = S.footprint_bytes(512, 128, 16384)
-    assert 16384 * (512 + 256) * 8 <= fb < 16384 * (512 + 256) * 8 * 1.2
+    # spectra [N_w][N_omega] and reconstructions [N_w][N_tau] in FP64, plus tables and per-walker scalars
+    assert 16384 * (512 + 128) * 8 <= fb < 16384 * (512 + 128) * 8 * 1.2
     assert S.footprint_bytes(0, 128, 10) == 0
 
 
