@@ -223,6 +223,27 @@ def test_deterministic_and_stageable(S, precision):
             assert np.array_equal(x, y)
 
 
+def test_staged_threshold_decides_like_the_fp64_log(S, monkeypatch):
+    """The accept threshold is staged from an FP32 logarithm and retaken in
+    FP64 inside its error band.  Forcing the FP64 retake for every decision
+    (diagnostic switch) must give the same bits, and that path also runs in
+    lockstep with the oracle."""
+    wl = W.config1()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    res = []
+    for exact in ("0", "1"):
+        monkeypatch.setenv("SAIL_EXACT_THRESHOLD", exact)
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.init_walkers(64, wl.seed)
+        gp.run(S.Schedule(T), 0, 300)
+        st = gp.read_state()
+        res.append((gp.read_chi2(), st["a"], st["F"], st["rate"]))
+    for x, y in zip(*res):
+        assert np.array_equal(x, y)
+    monkeypatch.setenv("SAIL_EXACT_THRESHOLD", "1")
+    _anneal_lockstep(S, wl, 64, wl.seed, 200)
+
+
 def test_outputs_match_oracle_definitions(S):
     wl = W.config1()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
