@@ -112,20 +112,34 @@ def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream) -> dict:
             "speedup_fp32_over_fp64": value32 / (wl.n_walkers * wl.omega.size * wl.n_sweeps / dt)}
 
 
-def cpu_baseline(wl, T, n_walkers, n_sweeps) -> dict:
+def cpu_baseline(wl, T, n_walkers, n_sweeps, one_thread_walkers=0) -> dict:
+    """The oracle on a walker sample of the workload, all host threads; with
+    one_thread_walkers > 0 also a smaller sample on one thread."""
     import oracle as O
     op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
-    stride = max(1, wl.n_walkers // n_walkers)
-    ids = np.arange(0, wl.n_walkers, stride)[:n_walkers]
-    # sweeps only: the sample's walkers are a subset, so no resync or branching
-    an = O.Anneal(op, O.Schedule(T, branch_every=10 ** 6, resync_every=10 ** 6), wl.n_walkers, wl.seed,
-                  walker_ids=ids)
-    t0 = time.perf_counter()
-    out = an.run(0, n_sweeps)
-    dt = time.perf_counter() - t0
-    return {"value": out["proposals"] / dt, "unit": "proposals/s", "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"{ids.size} of {wl.n_walkers} walkers (every {stride}th), sweeps 0-{n_sweeps - 1} of the same "
-                      f"schedule (sweeps only, no resync or branching): {out['proposals']} proposals in {dt:.2f} s"}
+
+    def sample(nw):
+        stride = max(1, wl.n_walkers // nw)
+        ids = np.arange(0, wl.n_walkers, stride)[:nw]
+        # sweeps only: the sample's walkers are a subset, so no resync or branching
+        an = O.Anneal(op, O.Schedule(T, branch_every=10 ** 6, resync_every=10 ** 6), wl.n_walkers, wl.seed,
+                      walker_ids=ids)
+        t0 = time.perf_counter()
+        out = an.run(0, n_sweeps)
+        return ids.size, stride, out["proposals"], time.perf_counter() - t0
+
+    threads = O.max_threads()
+    nw, stride, props, dt = sample(n_walkers)
+    res = {"value": props / dt, "unit": "proposals/s", "cores": threads, "kind": "oracle",
+           "sample": f"{nw} of {wl.n_walkers} walkers (every {stride}th), sweeps 0-{n_sweeps - 1} of the same "
+                     f"schedule (sweeps only, no resync or branching): {props} proposals in {dt:.2f} s"}
+    if one_thread_walkers > 0:
+        O.set_threads(1)
+        nw1, _, props1, dt1 = sample(one_thread_walkers)
+        O.set_threads(threads)
+        res["value_1_thread"] = props1 / dt1
+        res["sample_1_thread"] = f"{nw1} walkers, sweeps 0-{n_sweeps - 1}: {props1} proposals in {dt1:.2f} s"
+    return res
 
 
 def batched(args):
@@ -440,7 +454,8 @@ def main():
     if fp32 and steps * SWEEPS_PER_STEP == n_sweeps_total:
         line["vs_fp64"] = fp64_comparison(S, W, wl, T, gp, chi2, value, stream)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps)
+        line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps,
+                                            one_thread_walkers=max(1, args.cpu_sample_walkers // 16))
     print(json.dumps(line), flush=True)
 
 

@@ -98,6 +98,8 @@ def _declare(L: ctypes.CDLL) -> None:
     L.or_mean_spectrum.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
     L.or_chi2_hist.argtypes = [ctypes.c_int, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P]
     L.or_max_threads.restype = ctypes.c_int
+    L.or_set_threads.argtypes = [ctypes.c_int]
+    L.or_set_threads.restype = None
     L.or_move_deltas.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, P, P]
 
 
@@ -195,6 +197,10 @@ def move_deltas(omega, A: float, B: float, p: int, s: int, r: float) -> tuple[fl
 
 def max_threads() -> int:
     return int(lib().or_max_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

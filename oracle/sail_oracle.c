@@ -634,3 +634,13 @@ int or_max_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the number of OpenMP threads later calls use (n >= 1). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
