@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector
 SWEEPS_PER_STEP = 100
+# workload -> stem of its sweep-kernel summaries under profiles/
+WORKLOADS = {"fp64": "k_sweep_fp64_512x128x16384", "fp32": "k_sweep_fp32_512x128x16384",
+             "batched": "k_sweep_batched_fp32_256jobs", "served": None}
 
 
 def parse():
@@ -36,14 +39,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed blocks of 100 sweeps (200 = the whole anneal)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
-                    help="c2: FP64 loop (default); c3: FP32 loop with FP64 resync every 50 sweeps; "
-                         "c4: 256 mixed-size FP32 jobs in shared launches (a step is one round of 50 sweeps); "
-                         "c5: Poisson stream of c4-distributed jobs into the server")
-    ap.add_argument("--rate", type=float, default=50.0, help="c5: offered load, jobs/s")
-    ap.add_argument("--duration", type=float, default=30.0, help="c5: arrival window, s")
-    ap.add_argument("--max-jobs", type=int, default=256, help="c5: in-flight jobs at most")
-    ap.add_argument("--jobs", type=int, default=256, help="c4: number of jobs")
+    ap.add_argument("--workload", default="fp64", choices=list(WORKLOADS),
+                    help="fp64: 512 x 128 x 16384 walkers, FP64 loop (default); fp32: the same with the FP32 loop "
+                         "and FP64 resync every 50 sweeps; batched: 256 mixed-size FP32 jobs in shared launches "
+                         "(a step is one round of 50 sweeps); served: Poisson stream of such jobs into the server")
+    ap.add_argument("--rate", type=float, default=50.0, help="served: offered load, jobs/s")
+    ap.add_argument("--duration", type=float, default=30.0, help="served: arrival window, s")
+    ap.add_argument("--max-jobs", type=int, default=256, help="served: in-flight jobs at most")
+    ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -60,11 +63,13 @@ def sweep_source_digest() -> str:
     return hashlib.sha256(text[:j]).hexdigest()[:16]
 
 
-def measured_traffic(config: str):
+def measured_traffic(workload: str):
     """HBM bytes per sweep launch from the committed FETCH_SIZE / WRITE_SIZE
     summary, if it was taken on the sweep kernel's source as it stands (else
     None)."""
-    path = os.path.join(ROOT, "profiles", f"k_sweep_{config}_traffic.md")
+    if WORKLOADS[workload] is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{WORKLOADS[workload]}_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -86,7 +91,7 @@ def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream) -> dict:
     final residues, the FP32 path's largest sum-rule drift over the walkers,
     and its proposals/s against the FP64 path's."""
     import torch
-    c2 = W.config2()
+    fp64_wl = W.large_512x128()
     sp32 = gp32.read_spectrum(stream=stream)
     a32 = gp32.read_state(stream=stream)["a"]
     dw = wl.omega[1] - wl.omega[0]
@@ -96,7 +101,7 @@ def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream) -> dict:
     del a32
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP64, stream=stream)
-    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=c2.resync_every)
+    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=fp64_wl.resync_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(wl.n_sweeps // SWEEPS_PER_STEP):
@@ -143,7 +148,7 @@ def cpu_baseline(wl, T, n_walkers, n_sweeps, one_thread_walkers=0) -> dict:
 
 
 def batched(args):
-    """Config 4: 256 independent inversions of mixed sizes (N_omega in
+    """256 independent inversions of mixed sizes (N_omega in
     {128..1024}, N_tau in {32..256}, walkers in {256, 1024, 4096}), FP32 loop
     with FP64 resync every 50 sweeps, 1000 sweeps each, branching every 100;
     every round is one shared sweep launch plus shared resync / branch
@@ -231,7 +236,7 @@ def batched(args):
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": measured_traffic(args.config),
+            "traffic": measured_traffic(args.workload),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": sweep_ms / launches,
             "launches": launches,
@@ -255,7 +260,7 @@ def batched(args):
 
 
 def served(args):
-    """Config 5: jobs from config 4's distribution (1000 sweeps each) arrive
+    """Jobs of the batched workload's distribution (1000 sweeps each) arrive
     as a Poisson stream into the server; reports completed solves/s over the
     whole run and the submit-to-result latency percentiles, with sequential
     solo solves of the first jobs as the comparison."""
@@ -336,7 +341,7 @@ def served(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"Poisson arrivals at {args.rate:g} jobs/s for {args.duration:g} s of config-4 distributed "
+            "workload": f"Poisson arrivals at {args.rate:g} jobs/s for {args.duration:g} s of mixed-size "
                         "jobs (N_omega in {128..1024}, N_tau in {32..256}, walkers in {256,1024,4096}, 1000 "
                         "sweeps, FP32 loop, FP64 resync every 50, branching every 100) into one server "
                         f"(64 GiB arena, at most {args.max_jobs} in flight)",
@@ -365,9 +370,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the anneal runs on one device)",
               file=sys.stderr)
         sys.exit(2)
-    if args.config == "c4":
+    if args.workload == "batched":
         return batched(args)
-    if args.config == "c5":
+    if args.workload == "served":
         return served(args)
     import torch
     from paper_1609_07936_amd import sail as S
@@ -375,8 +380,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    fp32 = args.config == "c3"
-    wl = W.config3() if fp32 else W.config2()
+    fp32 = args.workload == "fp32"
+    wl = W.large_512x128_fp32() if fp32 else W.large_512x128()
     precision = S.SAIL_FP32 if fp32 else S.SAIL_FP64
     n_sweeps_total = wl.n_sweeps
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, n_sweeps_total)
@@ -444,7 +449,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic(args.config),
+            "traffic": measured_traffic(args.workload),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": avg_ms,
             "launches": launches,

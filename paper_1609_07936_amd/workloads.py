@@ -131,33 +131,34 @@ def two_peak_random(rng: np.random.Generator, omega_max: float, n_peaks: int = 2
     return Target(centres, widths, weights, omega_max)
 
 
-def config1(n_sweeps: int = 2000, n_walkers: int = 64) -> Workload:
+def small_64x32(n_sweeps: int = 2000, n_walkers: int = 64) -> Workload:
     """64 bins on [0, 10], 32 times on [0.05, 1.6], 0.6 L(1.5, 0.2) + 0.4 L(4, 0.5),
     noise 1e-4 F, 64 walkers, T 1e2 -> 1e-3 over 2000 sweeps, blocks of 100."""
     tgt = Target([1.5, 4.0], [0.2, 0.5], [0.6, 0.4], 10.0)
-    return make("c1", 10.0, 64, uniform_tau(0.05, 1.6, 32), tgt, 1e-4, 1, n_walkers, n_sweeps,
+    return make("small-64x32", 10.0, 64, uniform_tau(0.05, 1.6, 32), tgt, 1e-4, 1, n_walkers, n_sweeps,
                 1e2, 1e-3, 100, 100, 1)
 
 
-def config2(data_seed: int = 2, n_sweeps: int = 20000, n_walkers: int = 16384, resync_every: int = 100) -> Workload:
+def large_512x128(data_seed: int = 2, n_sweeps: int = 20000, n_walkers: int = 16384,
+                  resync_every: int = 100) -> Workload:
     """512 bins on [0, 20], 128 times on [0.02, 3], two seeded Lorentzians
     (centres U[0.5, 8], half-widths U[0.05, 1], weights w, 1-w), noise 1e-5 F,
     16384 walkers, T 1e3 -> 1e-2 over 20000 sweeps, blocks of 100."""
     rng = np.random.default_rng(data_seed)
     tgt = two_peak_random(rng, 20.0, 2)
-    return make("c2", 20.0, 512, uniform_tau(0.02, 3.0, 128), tgt, 1e-5, data_seed, n_walkers, n_sweeps,
+    return make("large-512x128", 20.0, 512, uniform_tau(0.02, 3.0, 128), tgt, 1e-5, data_seed, n_walkers, n_sweeps,
                 1e3, 1e-2, 100, resync_every, data_seed)
 
 
-def config3(data_seed: int = 2, n_sweeps: int = 20000, n_walkers: int = 16384) -> Workload:
-    """Config 2 with the FP32 residual loop and resync every 50 sweeps."""
-    wl = config2(data_seed, n_sweeps, n_walkers, resync_every=50)
-    wl.name = "c3"
+def large_512x128_fp32(data_seed: int = 2, n_sweeps: int = 20000, n_walkers: int = 16384) -> Workload:
+    """large_512x128 for the FP32 residual loop: resync every 50 sweeps."""
+    wl = large_512x128(data_seed, n_sweeps, n_walkers, resync_every=50)
+    wl.name = "large-512x128-fp32"
     return wl
 
 
 def batch_jobs(n_jobs: int = 256, base_seed: int = 1000, n_sweeps: int = 1000) -> list[Workload]:
-    """Config-4 style jobs: N_omega in {128..1024} on [0, 20], N_tau in
+    """Jobs of the mixed-size batch workload: N_omega in {128..1024} on [0, 20], N_tau in
     {32..256} on [0.02, 3], walkers in {256, 1024, 4096}, 2-3 peaks, noise
     log-uniform in [1e-6, 1e-3]."""
     jobs = []

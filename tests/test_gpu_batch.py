@@ -121,7 +121,7 @@ def test_batch_in_stages(S):
 
 
 def test_batch_errors(S):
-    wl = W.config1()
+    wl = W.small_64x32()
     sc = S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps))
     a = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     b = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)

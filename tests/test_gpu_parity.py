@@ -88,10 +88,10 @@ def _anneal_lockstep(S, wl, n_walkers, seed, n_sweeps, sched_kw=None, mode=0, si
     return gp, an, out
 
 
-def test_config1_full_anneal_lockstep(S):
-    """Config 1 end to end: 64 walkers x 2000 sweeps x 64 proposals, 20
+def test_small_full_anneal_lockstep(S):
+    """The small workload (64 bins, 32 times) end to end: 64 walkers x 2000 sweeps x 64 proposals, 20
     branching events; every proposal traced and compared."""
-    wl = W.config1()
+    wl = W.small_64x32()
     gp, an, out = _anneal_lockstep(S, wl, 64, wl.seed, wl.n_sweeps)
     assert out["proposals"] == 64 * 2000 * 64
     assert 0.2 < out["accepted"] / out["proposals"] < 0.8
@@ -127,10 +127,10 @@ def test_edge_shapes_lockstep(S, case):
 @pytest.mark.parametrize("walk_len", [1, 4])
 def test_selection_walk_lockstep(S, walk_len):
     """Sec. 2.3 index selection with a walk of independence Metropolis steps
-    on a_j / A: config 1, 64 walkers, 300 sweeps (three branching events),
+    on a_j / A: the small workload, 64 walkers, 300 sweeps (three branching events),
     every proposal traced against the oracle (a different chosen pair would
     change the residue change far beyond the bar)."""
-    wl = W.config1()
+    wl = W.small_64x32()
     _anneal_lockstep(S, wl, 64, wl.seed, 300, dict(walk_len=walk_len))
 
 
@@ -142,12 +142,12 @@ def test_selection_walk_ragged_tail(S):
     _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, dict(branch_every=60, resync_every=30, walk_len=2))
 
 
-def test_config2_full_size_sampled_lockstep(S):
-    """Config 2 at full size (16384 walkers, 512 bins, 128 times) in the
+def test_large_full_size_sampled_lockstep(S):
+    """The large workload at full size (16384 walkers, 512 bins, 128 times) in the
     launch configuration the benchmark times: three traced sweeps, checked on
     a sample of walkers that the oracle replays one by one."""
     import torch
-    wl = W.config2()
+    wl = W.large_512x128()
     n = wl.n_walkers
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
@@ -172,11 +172,11 @@ def test_config2_full_size_sampled_lockstep(S):
     np.testing.assert_allclose(st["a"][ids], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
 
 
-def test_config2_full_size_branching_event(S):
-    """The first branching event of config 2 at full size: the GPU's
+def test_large_full_size_branching_event(S):
+    """The first branching event of the large workload at full size: the GPU's
     multipliers equal the oracle's solve on the same residues, and every
     target holds t a_donor + (1 - t) a_target afterwards."""
-    wl = W.config2()
+    wl = W.large_512x128()
     n = wl.n_walkers
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     runs = {}
@@ -207,7 +207,7 @@ def test_deterministic_and_stageable(S, precision):
     """Two identical runs give identical bits, and a run split in stages at
     sweeps that are no resync boundary equals the run in one call (the state
     a launch leaves behind is all the next one needs)."""
-    wl = W.config1()
+    wl = W.small_64x32()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     res = []
     for stages in ([(0, 370)], [(0, 370)], [(0, 37), (37, 163), (163, 370)]):
@@ -228,7 +228,7 @@ def test_staged_threshold_decides_like_the_fp64_log(S, monkeypatch):
     FP64 inside its error band.  Forcing the FP64 retake for every decision
     (diagnostic switch) must give the same bits, and that path also runs in
     lockstep with the oracle."""
-    wl = W.config1()
+    wl = W.small_64x32()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     res = []
     for exact in ("0", "1"):
@@ -245,7 +245,7 @@ def test_staged_threshold_decides_like_the_fp64_log(S, monkeypatch):
 
 
 def test_outputs_match_oracle_definitions(S):
-    wl = W.config1()
+    wl = W.small_64x32()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     gp.init_walkers(64, wl.seed)
@@ -262,7 +262,7 @@ def test_outputs_match_oracle_definitions(S):
 
 
 def test_errors_leave_problem_usable(S):
-    wl = W.config1()
+    wl = W.small_64x32()
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     with pytest.raises(S.SailError):
         gp.run(S.Schedule(np.ones(10)), 0, 10)  # before init
@@ -281,13 +281,13 @@ def test_errors_leave_problem_usable(S):
 
 @pytest.mark.parametrize("tau_per_lane", [16, 32])
 def test_fp32_loop_first_sweeps_within_fp32_bar(S, tau_per_lane):
-    """FP32 residual loop (config 3's variant): every proposal of the first two
+    """FP32 residual loop (the variant the large FP32 workload runs): every proposal of the first two
     sweeps against the FP64 oracle, in both FP32 lane layouts.  The loop
-    carries Phi, G and the columns in FP32, so the bar is
+    carries Phi and the columns in FP32, so the bar is
     (TPL + log2 L + 8) u_32 M <= 1e-5 M; decisions whose margin falls inside
     that band are adopted by the oracle."""
     import torch
-    wl = W.config1()
+    wl = W.small_64x32()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     gp.set_tau_per_lane(tau_per_lane)
@@ -309,10 +309,10 @@ def test_fp32_loop_first_sweeps_within_fp32_bar(S, tau_per_lane):
 
 
 def test_fp32_anneal_quality_against_fp64(S):
-    """A whole config-1 anneal with the FP32 loop (FP64 resync every 50 sweeps)
+    """A whole anneal of the small workload with the FP32 loop (FP64 resync every 50 sweeps)
     lands in the same residue range as the FP64 path, and the FP64 resync keeps
     both sum rules to rounding."""
-    wl = W.config1()
+    wl = W.small_64x32()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     res = {}
     for prec, rs in ((S.SAIL_FP64, 100), (S.SAIL_FP32, 50)):
@@ -333,7 +333,7 @@ def test_fp32_anneal_quality_against_fp64(S):
 def test_checkpoint_resume_is_bit_exact(S):
     """Export after 250 sweeps, destroy, import into a fresh problem and
     continue: identical bits to the uninterrupted run (counter-based stream)."""
-    wl = W.config1()
+    wl = W.small_64x32()
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     ref = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     ref.init_walkers(64, wl.seed)

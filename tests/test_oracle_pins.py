@@ -199,15 +199,15 @@ def test_move_conserves_sums_and_is_reversible():
     assert O.move_deltas(om, A, B, 5, 5, 0.95) == (0.0, 0.0)
 
 
-def _c1_problem(noise_free=False, sigma=True):
-    wl = W.config1()
+def _small_problem(noise_free=False, sigma=True):
+    wl = W.small_64x32()
     Ft = wl.F_true if noise_free else wl.Ft
     return wl, O.Problem(wl.omega, wl.tau, Ft, wl.sigma if sigma else None, wl.m0, wl.m1)
 
 
 @pytest.mark.slow
 def test_sum_rule_drift_after_a_million_moves():
-    wl, prob = _c1_problem()
+    wl, prob = _small_problem()
     S = 36000
     sched = O.Schedule(np.full(S, 10.0), branch_every=10 ** 6, resync_every=10 ** 6)
     an = O.Anneal(prob, sched, 4, 3)
@@ -221,7 +221,7 @@ def test_sum_rule_drift_after_a_million_moves():
 
 
 def test_incremental_F_and_chi2_match_recomputation():
-    wl, prob = _c1_problem()
+    wl, prob = _small_problem()
     S = 300
     sched = O.Schedule(W.geometric_schedule(1e2, 1e-2, S), branch_every=10 ** 6, resync_every=10 ** 6)
     an = O.Anneal(prob, sched, 8, 5)
@@ -241,7 +241,7 @@ def test_first_proposal_dchi2_exact_rational():
     """The traced dchi^2 of each walker's first proposal (state known exactly)
     against chi^2(F + dF) - chi^2(F) in exact rational arithmetic, with the
     move rebuilt from the Philox words and the documented maps."""
-    wl, prob = _c1_problem()
+    wl, prob = _small_problem()
     sched = O.Schedule(W.geometric_schedule(1e2, 1e-3, 2000))
     an = O.Anneal(prob, sched, 16, wl.seed)
     F0 = an.F[0].copy()
@@ -302,7 +302,7 @@ def test_selection_walk_distribution_is_exact_markov_power(walk_len):
 
 
 def test_zero_temperature_never_raises_chi2_and_infinite_accepts_all_admissible():
-    wl, prob = _c1_problem()
+    wl, prob = _small_problem()
     S = 20
     for T, check in ((1e-300, "cold"), (1e300, "hot")):
         sched = O.Schedule(np.full(S, T), branch_every=10 ** 6, resync_every=10 ** 6)
@@ -430,7 +430,7 @@ def test_pairing_and_imprint_invariants():
     tg, dn = O.branch_pairs(m)
     assert tg.tolist() == [0, 3, 5, 7]
     assert dn.tolist() == [1, 1, 4, 8]
-    wl, prob = _c1_problem()
+    wl, prob = _small_problem()
     for t in (1.0, 0.1):
         sched = O.Schedule(W.geometric_schedule(1e2, 1e-3, 200), imprint_t=t)
         an = O.Anneal(prob, sched, 32, 4)
@@ -464,7 +464,7 @@ def test_pairing_and_imprint_invariants():
 # Outputs (Eq. residue-average)
 # --------------------------------------------------------------------------
 def test_outputs():
-    wl, prob = _c1_problem()
+    wl, prob = _small_problem()
     an = O.Anneal(prob, O.Schedule(W.geometric_schedule(1e2, 1e-3, 200)), 16, 2)
     an.run(0, 200)
     np.testing.assert_allclose(an.mean_spectrum(), an.a.mean(axis=0), rtol=1e-14)

@@ -28,16 +28,16 @@ def _closed_m1(target):
     return target.norm * tot
 
 
-def test_config1_quadrature_matches_exponential_integral():
-    wl = W.config1()
+def test_small_quadrature_matches_exponential_integral():
+    wl = W.small_64x32()
     ref = _closed_F(wl.target, wl.tau)
     np.testing.assert_allclose(wl.F_true, ref, rtol=1e-12)
     assert abs(wl.m0 - 1.0) < 1e-12
     assert abs(wl.m1 - _closed_m1(wl.target)) < 1e-11
 
 
-def test_config1_grids_and_noise():
-    wl = W.config1()
+def test_small_grids_and_noise():
+    wl = W.small_64x32()
     assert wl.omega.size == 64 and abs(wl.omega[1] - wl.omega[0] - 0.15625) < 1e-15
     assert abs(wl.omega[0] - 0.078125) < 1e-15
     assert wl.tau.size == 32 and abs(wl.tau[0] - 0.05) < 1e-15 and abs(wl.tau[-1] - 1.6) < 1e-14
@@ -49,8 +49,8 @@ def test_config1_grids_and_noise():
     assert abs(W.lorentzian_mass(4.0, 0.5, 10.0, np.inf) - 0.0265) < 5e-4
 
 
-def test_config2_family_and_quadrature():
-    wl = W.config2(n_sweeps=10, n_walkers=16)
+def test_large_family_and_quadrature():
+    wl = W.large_512x128(n_sweeps=10, n_walkers=16)
     t = wl.target
     assert np.all((t.centres >= 0.5) & (t.centres <= 8.0))
     assert np.all((t.widths >= 0.05) & (t.widths <= 1.0))
@@ -59,7 +59,7 @@ def test_config2_family_and_quadrature():
     np.testing.assert_allclose(wl.F_true, _closed_F(t, wl.tau), rtol=1e-10)
     np.testing.assert_allclose(wl.sigma, 1e-5 * wl.F_true, rtol=1e-15)
     # seeded: the same data seed reproduces the same inputs
-    wl2 = W.config2(n_sweeps=10, n_walkers=16)
+    wl2 = W.large_512x128(n_sweeps=10, n_walkers=16)
     assert np.array_equal(wl.Ft, wl2.Ft)
 
 
