@@ -50,7 +50,9 @@ def _check_trace(g_d, g_f, out):
     cond = out["cond"]
     err = np.abs(g_d - out["dchi2"])
     bad = err > 1e-12 * cond
-    assert not bad.any(), f"{bad.sum()} proposals outside 1e-12 M; worst {np.max(err / np.maximum(cond, 1e-300)):.3e}"
+    worst = float(np.max(err / np.maximum(cond, 1e-300)))
+    print(f"worst |dchi2 error| / M over {err.size} proposals: {worst:.3e}", flush=True)
+    assert not bad.any(), f"{bad.sum()} proposals outside 1e-12 M; worst {worst:.3e}"
     assert out["hard_mismatch"] == 0, f"hard mismatches at {out['first_mismatch']}"
     # after adopting near-ties the accept bits agree everywhere
     np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
