@@ -100,11 +100,13 @@ def test_small_full_anneal_lockstep(S):
     assert np.all(an.ev_status[:20] == 0)
 
 
-@pytest.mark.parametrize("case", ["ragged", "bin_exact_unweighted", "single_tau", "two_walkers", "wide"])
+@pytest.mark.parametrize("case", ["ragged", "bin_exact_unweighted", "single_tau", "two_walkers", "wide", "steep"])
 def test_edge_shapes_lockstep(S, case):
     """Ragged walker counts and tau padding, the exact-bin kernel with the
-    paper's unweighted residue, one tau point, the smallest population, and
-    the widest lane layout."""
+    paper's unweighted residue, one tau point, the smallest population, the
+    widest lane layout, and a steep kernel whose columns span the whole FP64
+    range and underflow to zero (e^{-omega dtau} down to 1e-14 per step,
+    e^{-omega tau} down to e^{-1000})."""
     rng = np.random.default_rng(77)
     tgt = W.Target([1.2, 3.0], [0.3, 0.6], [0.5, 0.5], 6.0)
     if case == "ragged":
@@ -119,10 +121,14 @@ def test_edge_shapes_lockstep(S, case):
     elif case == "two_walkers":
         wl = W.make("t", 6.0, 24, W.uniform_tau(0.1, 1.0, 10), tgt, 1e-4, 6, 2, 100, 1e1, 1e-2, 50, 50, 8)
         kw, mode, sigma = dict(branch_every=50, resync_every=50, branch_fraction=0.5), 0, True
-    else:
+    elif case == "wide":
         wl = W.make("w", 20.0, 1024, W.uniform_tau(0.02, 3.0, 256), W.two_peak_random(rng, 20.0), 1e-5, 9, 48, 4,
                     1e3, 1e-2, 2, 1, 10, n_quad=20000)
         kw, mode, sigma = dict(branch_every=2, resync_every=1), 0, True
+    else:
+        steep = W.Target([5.0, 20.0], [2.0, 5.0], [0.5, 0.5], 100.0)
+        wl = W.make("st", 100.0, 64, W.uniform_tau(0.02, 10.0, 32), steep, 1e-4, 11, 40, 200, 1e2, 1e-3, 100, 50, 12)
+        kw, mode, sigma = dict(branch_every=100, resync_every=50), 0, True
     _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma)
 
 
