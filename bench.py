@@ -9,7 +9,7 @@ FP64 configuration: 512 bins on [0, 20], 128 times on [0.02, 3], 16384
 walkers, 20000 sweeps (200 steps), double-Lorentzian synthetic data with
 1e-5 relative noise.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line (see the driver contract): the metric, the roofline
+Prints one JSON line: the metric, the roofline
 of the sweep kernel from HIP events on its launch stream, and the CPU
 oracle timed on a bounded sample of the same workload.
 """

@@ -204,7 +204,7 @@ def set_threads(n: int) -> None:
 
 
 # --------------------------------------------------------------------------
-# problem + anneal driver
+# problem + anneal runner
 # --------------------------------------------------------------------------
 @dataclass
 class Problem:
