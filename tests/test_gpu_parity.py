@@ -180,6 +180,40 @@ def test_large_full_size_sampled_lockstep(S):
     np.testing.assert_allclose(st["a"][ids], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
 
 
+def test_large_fp32_full_size_sampled_within_fp32_bar(S):
+    """The FP32 loop at full size (16384 walkers, 512 bins, 128 times) in the
+    launch configuration the benchmark times for it: three traced sweeps
+    against the FP64 oracle on a sample of walkers, inside the FP32 bar
+    (decisions within that band adopted by the oracle)."""
+    import torch
+    wl = W.large_512x128_fp32()
+    n = wl.n_walkers
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(n, wl.seed, precision=S.SAIL_FP32)
+    assert gp.layout() == (8, 16)
+    ns = 3
+    d, f = _trace_buffers(n, ns, wl.omega.size)
+    gp.set_trace(0, ns, d.data_ptr(), f.data_ptr())
+    gp.run(S.Schedule(T, resync_every=wl.resync_every), 0, ns)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    ids = np.unique(np.concatenate([[0, 1, 7, 8, 63, 64, 4095, 8191, 16383], rng.choice(n, 23, replace=False)]))
+    g_d, g_f = d[ids].cpu().numpy(), f[ids].cpu().numpy()
+    del d, f
+    op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    an = O.Anneal(op, O.Schedule(T, resync_every=wl.resync_every), n, wl.seed, walker_ids=ids)
+    out = an.run(0, ns, trace=(0, ns), replay=g_f, band=1e-5)
+    assert out["hard_mismatch"] == 0, out["first_mismatch"]
+    err = np.abs(g_d - out["dchi2"])
+    worst = float(np.max(err / np.maximum(out["cond"], 1e-300)))
+    print(f"worst |dchi2 error| / M over {err.size} proposals: {worst:.3e}", flush=True)
+    assert np.all(err <= 1e-5 * out["cond"]), worst
+    np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
+    st = gp.read_state()
+    np.testing.assert_allclose(st["a"][ids], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
+
+
 def test_large_full_size_branching_event(S):
     """The first branching event of the large workload at full size: the GPU's
     multipliers equal the oracle's solve on the same residues, and every
