@@ -74,6 +74,7 @@ class AnnealArgs(ctypes.Structure):
         ("n_proposals", ctypes.c_int64), ("n_accepted", ctypes.c_int64),
         ("first_mismatch", ctypes.c_int32 * 3),
         ("trace_p", ctypes.c_void_p), ("trace_s", ctypes.c_void_p),
+        ("smooth", ctypes.c_double),
     ]
 
 
@@ -86,6 +87,7 @@ def _declare(L: ctypes.CDLL) -> None:
     L.or_chi2.argtypes = [P, P, P, ctypes.c_int]
     L.or_chi2.restype = ctypes.c_double
     L.or_renormalize.argtypes = [P, P, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    L.or_smooth.argtypes = [P, ctypes.c_int, ctypes.c_double]
     L.or_init_spectrum.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P]
     L.or_init_spectrum.restype = ctypes.c_int
     L.or_branch_solve.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P, P]
@@ -147,6 +149,13 @@ def renormalize(a, omega, A: float, B: float) -> np.ndarray:
     a = _f64(a).copy()
     om = _f64(omega)
     lib().or_renormalize(_p(a), _p(om), om.size, float(A), float(B))
+    return a
+
+
+def smooth(a, s: float) -> np.ndarray:
+    """The three-point smoothing stencil of Sec. 2.6 with amplitude s."""
+    a = _f64(a).copy()
+    lib().or_smooth(_p(a), a.size, float(s))
     return a
 
 
@@ -249,6 +258,7 @@ class Schedule:
     amp_m: int = 2
     amp_avg: float = 0.1
     walk_len: int = 0
+    smooth: float = 0.0
 
 
 def geometric_schedule(t_hi: float, t_lo: float, n_sweeps: int) -> np.ndarray:
@@ -285,6 +295,7 @@ class Anneal:
         g.branch_fraction, g.imprint_t = sched.branch_fraction, sched.imprint_t
         g.eps0, g.amp_p, g.amp_m, g.walk_len = sched.eps0, sched.amp_p, sched.amp_m, sched.walk_len
         g.amp_avg = sched.amp_avg
+        g.smooth = sched.smooth
         g.seed = self.seed
         g.trace_k0 = g.trace_k1 = 0
         g.band = 1e-12

@@ -139,6 +139,27 @@ void or_renormalize(double *a, const double *omega, int n, double A, double B)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Smoothing (Sec. 2.6): the three-point stencil with amplitude s,          */
+/*   a_j <- s a_{j-1} + (1 - 2s) a_j + s a_{j+1}   for 0 < j < n - 1,        */
+/*   a_0 <- (1 - s) a_0 + s a_1,  a_{n-1} <- (1 - s) a_{n-1} + s a_{n-2},   */
+/* all on the values before the update.  It keeps sum_j a_j; the second sum */
+/* needs the renormalisation above.                                          */
+/* ------------------------------------------------------------------------ */
+void or_smooth(double *a, int n, double s)
+{
+    if (n < 2) return;
+    const double c = 1.0 - 2.0 * s, e = 1.0 - s;
+    double prev = a[0];
+    a[0] = e * a[0] + s * a[1];
+    for (int j = 1; j < n - 1; ++j) {
+        const double cur = a[j];
+        a[j] = s * prev + c * cur + s * a[j + 1];
+        prev = cur;
+    }
+    a[n - 1] = e * a[n - 1] + s * prev;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Initial spectrum.  The paper does not say how walkers start.  Reading:   */
 /* the maximum-entropy spectrum that meets both sum rules, a_j ~ e^{-lambda */
 /* omega_j}, with lambda found by bisection on the mean frequency B/A, then */
@@ -373,6 +394,11 @@ typedef struct {
     /* optional: the two bins each traced proposal chose (after the
      * selection walk), same layout as the other traces */
     int32_t *trace_p, *trace_s;
+    /* smoothing amplitude s of Sec. 2.6 (0: none).  Reading: after every
+     * branching event each walker is smoothed, renormalised, and its F and
+     * chi^2 recomputed, so the next block's sweeps start from smoothed
+     * spectra */
+    double smooth;
 } or_anneal_args;
 
 typedef struct { int64_t near, hard, props, acc; int32_t fk, fq; } walker_log;
@@ -564,7 +590,16 @@ int or_anneal(or_anneal_args *g, int k0, int k1, double *a, double *F, double *c
 #pragma omp parallel for schedule(static)
             for (int l = 0; l < n; ++l) resync_walker(g, a + (size_t)l * No, F + (size_t)l * Nt, chi2 + l);
         }
-        if (kend % g->branch_every == 0) branch_event(g, kend / g->branch_every - 1, a, F, chi2);
+        if (kend % g->branch_every == 0) {
+            branch_event(g, kend / g->branch_every - 1, a, F, chi2);
+            if (g->smooth > 0.0) {
+#pragma omp parallel for schedule(static)
+                for (int l = 0; l < n; ++l) {
+                    or_smooth(a + (size_t)l * No, No, g->smooth);
+                    resync_walker(g, a + (size_t)l * No, F + (size_t)l * Nt, chi2 + l);
+                }
+            }
+        }
         k = kend;
     }
     int64_t near = 0, hard = 0, props = 0, acc = 0;

@@ -461,6 +461,78 @@ def test_pairing_and_imprint_invariants():
 
 
 # --------------------------------------------------------------------------
+# Smoothing (Sec. 2.6)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3, 17, 64])
+def test_smoothing_acts_on_cosine_modes_by_the_laplacian_eigenvalue(n):
+    """The stencil is a + s L a with L the three-point Laplacian whose end
+    rows reflect (a ghost a_{-1} = a_0); the cosine modes cos(pi k (j + 1/2) / n)
+    are its eigenvectors with eigenvalue -4 sin^2(pi k / 2n), so the smoothed
+    mode is the mode times 1 - 4 s sin^2(pi k / 2n).  A dropped end term, a
+    wrong sign or an updated-in-place neighbour breaks it."""
+    j = np.arange(n) + 0.5
+    for s_amp in (0.0, 0.01, 0.2, 0.5):
+        for k in range(n):
+            v = np.cos(np.pi * k * j / n)
+            lam = 1.0 - 4.0 * s_amp * np.sin(np.pi * k / (2 * n)) ** 2
+            np.testing.assert_allclose(O.smooth(v, s_amp), lam * v, rtol=0, atol=1e-13)
+
+
+def test_smoothing_keeps_the_first_sum_and_moves_the_second_by_the_end_values():
+    """Sum_j a_j is kept; on a uniform grid sum_j omega_j a_j moves by exactly
+    s d_omega (a_0 - a_{n-1}) (the telescoped flux of the stencil, the size
+    of the violation the paper quotes); after the renormalisation both sums
+    hold again.  s = 0 is the identity."""
+    rng = np.random.default_rng(5)
+    wl, prob = _small_problem()
+    om = wl.omega
+    dw = om[1] - om[0]
+    for _ in range(50):
+        a = rng.uniform(0.0, 1.0, om.size)
+        a *= prob.A / a.sum()
+        s_amp = rng.uniform(0.0, 0.5)
+        b = O.smooth(a, s_amp)
+        assert abs(b.sum() - a.sum()) <= 1e-14 * a.sum()
+        d1 = (b * om).sum() - (a * om).sum()
+        assert abs(d1 - s_amp * dw * (a[0] - a[-1])) <= 1e-13 * (a * om).sum()
+        assert np.all(b >= 0.0)
+        c = O.renormalize(b, om, prob.A, prob.B)
+        assert abs(c.sum() - prob.A) <= 1e-13 * prob.A
+        assert abs((c * om).sum() - prob.B) <= 1e-13 * prob.B
+    a = rng.uniform(0.0, 1.0, om.size)
+    assert np.array_equal(O.smooth(a, 0.0), a)
+
+
+def test_smoothing_in_the_anneal_follows_each_branching_event():
+    """With s > 0 the anneal equals the unsmoothed one up to the first
+    branching event; right after it every walker holds the renormalised
+    smoothing of its post-imprint spectrum, with F and chi^2 recomputed."""
+    wl, prob = _small_problem()
+    T = W.geometric_schedule(1e2, 1e-3, 300)
+    base = O.Anneal(prob, O.Schedule(T), 24, 9)
+    smo = O.Anneal(prob, O.Schedule(T, smooth=0.05), 24, 9)
+    base.run(0, 100)
+    smo.run(0, 99)
+    pre = smo.a.copy()
+    smo.run(99, 100)
+    assert base.ev_status[0] == smo.ev_status[0] == 0
+    np.testing.assert_array_equal(base.ev_m[0], smo.ev_m[0])
+    ref = base.a  # the same event without smoothing
+    base99 = O.Anneal(prob, O.Schedule(T), 24, 9)
+    base99.run(0, 99)
+    np.testing.assert_array_equal(pre, base99.a)
+    for l in range(24):
+        expect = O.renormalize(O.smooth(ref[l], 0.05), wl.omega, prob.A, prob.B)
+        np.testing.assert_allclose(smo.a[l], expect, rtol=1e-13, atol=0)
+        np.testing.assert_allclose(smo.F[l], O.forward(prob.K, smo.a[l]), rtol=1e-13)
+        assert abs(smo.chi2[l] - O.chi2(smo.F[l], prob.Ft, prob.w)) <= 1e-12 * smo.chi2[l]
+    assert not np.array_equal(smo.a, ref)
+    smo.run(100, 300)
+    assert np.all(np.abs(smo.a.sum(axis=1) - prob.A) <= 1e-12 * prob.A)
+    assert np.all(np.abs((smo.a * wl.omega).sum(axis=1) - prob.B) <= 1e-12 * prob.B)
+
+
+# --------------------------------------------------------------------------
 # Outputs (Eq. residue-average)
 # --------------------------------------------------------------------------
 def test_outputs():
