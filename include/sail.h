@@ -77,6 +77,11 @@ typedef struct {
     int walk_len;           /* steps of the index-selection walk of Sec. 2.3, 0..64 (0: uniform) [0];
                                walks run through sail_run_schedule only */
     int t_units;            /* 0: T in units of the starting residue (Sec. 3); 1: absolute */
+    double smooth;          /* amplitude s of the three-point smoothing stencil of Sec. 2.6, [0, 0.5]
+                               (0: off) [0]: after every branching event each walker's spectrum is
+                               smoothed (a_j <- s a_{j-1} + (1 - 2s) a_j + s a_{j+1}, ends
+                               (1 - s) a_end + s a_next), both sums renormalised, F and chi^2
+                               recomputed; smoothing runs through sail_run_schedule only */
 } sail_schedule;
 
 /* Fills *s with the defaults above and T = NULL, n_T = 0. */

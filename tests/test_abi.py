@@ -30,6 +30,30 @@ def test_every_declared_symbol_is_exported(S):
     assert not missing, missing
 
 
+def test_binding_structs_match_the_header(S, tmp_path):
+    """Every struct the binding passes by pointer has the size and field
+    offsets the C compiler gives the header's declaration."""
+    structs = {"sail_schedule": S.ScheduleC, "sail_job": S.JobC, "sail_job_result": S.JobResultC,
+               "sail_server_stats": S.ServerStatsC, "sail_server_config": S.ServerConfigC}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sail.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
 def test_host_only_entry_points(S):
     L = S.lib()
     sc = S.ScheduleC()

@@ -144,6 +144,8 @@ def test_batch_errors(S):
     a.set_trace(0, 0)
     with pytest.raises(S.SailError):  # selection walks run through the single-problem path
         batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), walk_len=2), 0, 5)
+    with pytest.raises(S.SailError):  # so does smoothing
+        batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), smooth=0.01), 0, 5)
     batch.run(sc, 0, 5)
     torch.cuda.synchronize()
 

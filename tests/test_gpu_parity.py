@@ -132,6 +132,22 @@ def test_edge_shapes_lockstep(S, case):
     _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma)
 
 
+@pytest.mark.parametrize("case", ["small", "three_chunks"])
+def test_smoothing_lockstep(S, case):
+    """Sec. 2.6 smoothing after every branching event (renormalised, F and
+    chi^2 recomputed), every proposal traced against the oracle: the small
+    workload (one 64-lane chunk per row), and 150 bins whose rows span three
+    chunks with a ragged end (the value left of each chunk is carried)."""
+    if case == "small":
+        wl = W.small_64x32()
+        _anneal_lockstep(S, wl, 64, wl.seed, 300, dict(smooth=0.05))
+    else:
+        tgt = W.Target([1.5, 4.0], [0.3, 0.8], [0.5, 0.5], 8.0)
+        wl = W.make("sm", 8.0, 150, W.uniform_tau(0.05, 1.5, 24), tgt, 1e-4, 13, 20, 300, 1e2, 1e-3, 100, 50, 14)
+        _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, dict(branch_every=100, resync_every=50,
+                                                                         smooth=0.2))
+
+
 @pytest.mark.parametrize("walk_len", [1, 4])
 def test_selection_walk_lockstep(S, walk_len):
     """Sec. 2.3 index selection with a walk of independence Metropolis steps
