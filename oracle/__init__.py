@@ -74,7 +74,7 @@ class AnnealArgs(ctypes.Structure):
         ("n_proposals", ctypes.c_int64), ("n_accepted", ctypes.c_int64),
         ("first_mismatch", ctypes.c_int32 * 3),
         ("trace_p", ctypes.c_void_p), ("trace_s", ctypes.c_void_p),
-        ("smooth", ctypes.c_double),
+        ("smooth", ctypes.c_double), ("adaptive", ctypes.c_int),
     ]
 
 
@@ -259,6 +259,7 @@ class Schedule:
     amp_avg: float = 0.1
     walk_len: int = 0
     smooth: float = 0.0
+    adaptive: int = 0
 
 
 def geometric_schedule(t_hi: float, t_lo: float, n_sweeps: int) -> np.ndarray:
@@ -296,6 +297,7 @@ class Anneal:
         g.eps0, g.amp_p, g.amp_m, g.walk_len = sched.eps0, sched.amp_p, sched.amp_m, sched.walk_len
         g.amp_avg = sched.amp_avg
         g.smooth = sched.smooth
+        g.adaptive = int(sched.adaptive)
         g.seed = self.seed
         g.trace_k0 = g.trace_k1 = 0
         g.band = 1e-12

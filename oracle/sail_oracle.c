@@ -399,6 +399,10 @@ typedef struct {
      * chi^2 recomputed, so the next block's sweeps start from smoothed
      * spectra */
     double smooth;
+    /* adaptive branching (Sec. 2.5, last paragraph).  Reading: at each event
+     * the branching fraction and the imprint strength are scaled by the
+     * population mean of the running acceptance rate (which starts at 1) */
+    int adaptive;
 } or_anneal_args;
 
 typedef struct { int64_t near, hard, props, acc; int32_t fk, fq; } walker_log;
@@ -522,8 +526,9 @@ static void resync_walker(const or_anneal_args *g, double *a, double *F, double 
 }
 
 /* One branching event (Sec. 2.5): xi_l from the branching stream, solve,
- * pair, imprint a^(l1) <- t a^(l2) + (1 - t) a^(l1), recompute F, chi^2. */
-static int branch_event(or_anneal_args *g, int e, double *a, double *F, double *chi2)
+ * pair, imprint a^(l1) <- t a^(l2) + (1 - t) a^(l1), recompute F, chi^2.
+ * With adaptive branching the fraction and t are scaled by the mean rate. */
+static int branch_event(or_anneal_args *g, int e, double *a, double *F, double *chi2, const double *rate)
 {
     const int n = g->n_walkers, No = g->n_omega, Nt = g->n_tau;
     double *xi = (double *)malloc(sizeof(double) * (size_t)n);
@@ -535,8 +540,16 @@ static int branch_event(or_anneal_args *g, int e, double *a, double *F, double *
         draw(g->seed, (uint32_t)l, (uint32_t)e, 0u, OR_STREAM_BRANCH, x);
         xi[l] = u01(x[0]);
     }
+    double fraction = g->branch_fraction, t = g->imprint_t;
+    if (g->adaptive) {
+        double mean = 0.0;
+        for (int l = 0; l < n; ++l) mean += rate[l];
+        mean /= (double)n;
+        fraction *= mean;
+        t *= mean;
+    }
     double delta, pr; int z, tie;
-    int st = or_branch_solve(n, chi2, xi, g->branch_fraction, &delta, &pr, m, &z, &tie);
+    int st = or_branch_solve(n, chi2, xi, fraction, &delta, &pr, m, &z, &tie);
     if (st == 0 && tie) st = 2; /* A tie leaves sum m = n ambiguous: skip. */
     if (st != 0) for (int l = 0; l < n; ++l) m[l] = 1;
     if (g->ev_status && e < g->max_events) {
@@ -548,7 +561,6 @@ static int branch_event(or_anneal_args *g, int e, double *a, double *F, double *
     }
     if (st == 0) {
         int np = or_branch_pairs(n, m, tg, dn);
-        double t = g->imprint_t;
         for (int c = 0; c < np; ++c) {
             double *a1 = a + (size_t)tg[c] * No;
             const double *a2 = a + (size_t)dn[c] * No;
@@ -591,7 +603,7 @@ int or_anneal(or_anneal_args *g, int k0, int k1, double *a, double *F, double *c
             for (int l = 0; l < n; ++l) resync_walker(g, a + (size_t)l * No, F + (size_t)l * Nt, chi2 + l);
         }
         if (kend % g->branch_every == 0) {
-            branch_event(g, kend / g->branch_every - 1, a, F, chi2);
+            branch_event(g, kend / g->branch_every - 1, a, F, chi2, rate);
             if (g->smooth > 0.0) {
 #pragma omp parallel for schedule(static)
                 for (int l = 0; l < n; ++l) {

@@ -460,6 +460,36 @@ def test_pairing_and_imprint_invariants():
         assert np.array_equal(before[keep], pre[keep])
 
 
+def test_adaptive_branching_scales_fraction_and_imprint_by_the_mean_rate():
+    """Adaptive branching (Sec. 2.5, last paragraph): an event is the plain
+    event (whose solve and imprint are pinned above) at branching fraction
+    f * rho and imprint strength t * rho, rho the population mean of the
+    running acceptance rates at the event; the state before it is untouched."""
+    wl, prob = _small_problem()
+    T = W.geometric_schedule(1e2, 1e-3, 300)
+    for k_ev in (100, 300):
+        ad = O.Anneal(prob, O.Schedule(T, adaptive=1), 32, 4)
+        ad.run(0, k_ev - 1)
+        ref = O.Anneal(prob, O.Schedule(T, adaptive=1), 32, 4)
+        ref.run(0, k_ev - 1)
+        ref.args.branch_every = 10 ** 6
+        ref.run(k_ev - 1, k_ev)  # the same sweep and resync, no event
+        ad.run(k_ev - 1, k_ev)
+        e = k_ev // 100 - 1
+        rho = ref.rate.mean()
+        assert 0.0 < rho < 1.0
+        res = O.branch_solve(ref.chi2, O.branch_xi(4, e, 32), 0.25 * rho)
+        assert ad.ev_status[e] == res["status"]
+        np.testing.assert_array_equal(ad.ev_m[e], res["m"])
+        assert ad.ev_z[e] == res["z"]
+        tg, dn = O.branch_pairs(res["m"])
+        assert res["status"] == 0 and len(tg) == res["z"] > 0
+        t = 0.1 * rho
+        np.testing.assert_allclose(ad.a[tg], t * ref.a[dn] + (1.0 - t) * ref.a[tg], rtol=1e-15, atol=0)
+        keep = np.setdiff1d(np.arange(32), tg)
+        assert np.array_equal(ad.a[keep], ref.a[keep])
+
+
 # --------------------------------------------------------------------------
 # Smoothing (Sec. 2.6)
 # --------------------------------------------------------------------------
