@@ -82,6 +82,10 @@ typedef struct {
                                smoothed (a_j <- s a_{j-1} + (1 - 2s) a_j + s a_{j+1}, ends
                                (1 - s) a_end + s a_next), both sums renormalised, F and chi^2
                                recomputed; smoothing runs through sail_run_schedule only */
+    int adaptive;           /* 1: adaptive branching (Sec. 2.5, last paragraph) [0]: each event uses
+                               branch_fraction and imprint_t scaled by the population mean of the
+                               walkers' running acceptance rates (which start at 1); runs through
+                               sail_run_schedule only */
 } sail_schedule;
 
 /* Fills *s with the defaults above and T = NULL, n_T = 0. */

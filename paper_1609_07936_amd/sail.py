@@ -33,7 +33,7 @@ class ScheduleC(ctypes.Structure):
         ("branch_fraction", ctypes.c_double), ("imprint_t", ctypes.c_double),
         ("eps0", ctypes.c_double), ("amp_p", ctypes.c_double), ("amp_m", ctypes.c_int),
         ("amp_avg", ctypes.c_double), ("walk_len", ctypes.c_int), ("t_units", ctypes.c_int),
-        ("smooth", ctypes.c_double),
+        ("smooth", ctypes.c_double), ("adaptive", ctypes.c_int),
     ]
 
 
@@ -197,7 +197,8 @@ class Schedule:
     running-average weight of the acceptance rate."""
 
     def __init__(self, T, branch_every=100, resync_every=100, branch_fraction=0.25, imprint_t=0.1, eps0=0.1,
-                 amp_p=1.0, amp_m=2, amp_avg=0.1, walk_len=0, t_units=0, smooth=0.0):
+                 amp_p=1.0, amp_m=2, amp_avg=0.1, walk_len=0, t_units=0, smooth=0.0,
+                 adaptive=0):
         self.T = _f64(T)
         self.c = ScheduleC()
         lib().sail_schedule_defaults(ctypes.byref(self.c))
@@ -208,6 +209,7 @@ class Schedule:
         c.amp_p, c.amp_m, c.amp_avg = float(amp_p), int(amp_m), float(amp_avg)
         c.walk_len, c.t_units = int(walk_len), int(t_units)
         c.smooth = float(smooth)
+        c.adaptive = int(adaptive)
 
     @property
     def n_sweeps(self) -> int:

@@ -148,6 +148,19 @@ def test_smoothing_lockstep(S, case):
                                                                          smooth=0.2))
 
 
+@pytest.mark.parametrize("smooth", [0.0, 0.01])
+def test_adaptive_branching_lockstep(S, smooth):
+    """Adaptive branching (fraction and imprint strength scaled by the mean
+    running acceptance rate at each event), alone and with smoothing: the
+    small workload end to end, every proposal, event and final state against
+    the oracle (the mean is summed in a different order on each side; the
+    zero-count targets agree unless f rho N lands within rounding of a half)."""
+    wl = W.small_64x32()
+    gp, an, out = _anneal_lockstep(S, wl, 64, wl.seed, wl.n_sweeps, dict(adaptive=1, smooth=smooth))
+    z = an.ev_z[:20]
+    assert np.all(an.ev_status[:20] == 0) and z[-1] < z[0]  # fewer walkers branched as acceptance falls
+
+
 @pytest.mark.parametrize("walk_len", [1, 4])
 def test_selection_walk_lockstep(S, walk_len):
     """Sec. 2.3 index selection with a walk of independence Metropolis steps
