@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--duration", type=float, default=30.0, help="served: arrival window, s")
     ap.add_argument("--max-jobs", type=int, default=256, help="served: in-flight jobs at most")
     ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
+    ap.add_argument("--smooth", type=float, default=0.0,
+                    help="fp64/fp32: smoothing amplitude of Sec. 2.6 after every branching event (paper: 0.01)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="fp64/fp32: adaptive branching (fraction and imprint scaled by the mean acceptance rate)")
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -82,7 +86,7 @@ def measured_traffic(workload: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream) -> dict:
+def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream, smooth=0.0, adaptive=0) -> dict:
     """The FP32-loop anneal against the FP64 path (the FP64 GPU path is
     parity-tested against the CPU oracle; the oracle itself would take hours
     at this size): the same walkers, seeds and schedule with resync every 100
@@ -101,7 +105,8 @@ def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream) -> dict:
     del a32
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP64, stream=stream)
-    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=fp64_wl.resync_every)
+    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=fp64_wl.resync_every, smooth=smooth,
+                       adaptive=adaptive)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(wl.n_sweeps // SWEEPS_PER_STEP):
@@ -390,7 +395,8 @@ def main():
         raise SystemExit("steps exceed the schedule")
     stream = torch.cuda.current_stream()
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
-    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=wl.resync_every)
+    sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=wl.resync_every, smooth=args.smooth,
+                       adaptive=int(args.adaptive))
     gp.init_walkers(wl.n_walkers, wl.seed, precision=precision, stream=stream)
     for s in range(warm):
         gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
@@ -436,6 +442,7 @@ def main():
                         "noise 1e-5 F",
             "n_omega": int(wl.omega.size), "n_tau": int(wl.tau.size), "n_walkers": int(wl.n_walkers),
             "sweeps_timed": SWEEPS_PER_STEP * steps, "precision": "fp32 loop" if fp32 else "fp64",
+            "smooth": args.smooth, "adaptive_branching": bool(args.adaptive),
         },
         "quality": {
             "final_chi2_over_chi2_0_median": float(np.median(chi2) / gp.chi2_unit),
@@ -457,7 +464,7 @@ def main():
         },
     }
     if fp32 and steps * SWEEPS_PER_STEP == n_sweeps_total:
-        line["vs_fp64"] = fp64_comparison(S, W, wl, T, gp, chi2, value, stream)
+        line["vs_fp64"] = fp64_comparison(S, W, wl, T, gp, chi2, value, stream, args.smooth, int(args.adaptive))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps,
                                             one_thread_walkers=max(1, args.cpu_sample_walkers // 16))
