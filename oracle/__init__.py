@@ -75,6 +75,8 @@ class AnnealArgs(ctypes.Structure):
         ("first_mismatch", ctypes.c_int32 * 3),
         ("trace_p", ctypes.c_void_p), ("trace_s", ctypes.c_void_p),
         ("smooth", ctypes.c_double), ("adaptive", ctypes.c_int),
+        ("self_cool", ctypes.c_int), ("boil_blocks", ctypes.c_int), ("cool_blocks", ctypes.c_int),
+        ("T_self", ctypes.c_void_p),
     ]
 
 
@@ -260,6 +262,9 @@ class Schedule:
     walk_len: int = 0
     smooth: float = 0.0
     adaptive: int = 0
+    self_cool: int = 0
+    boil_blocks: int = 0
+    cool_blocks: int = 1
 
 
 def geometric_schedule(t_hi: float, t_lo: float, n_sweeps: int) -> np.ndarray:
@@ -298,6 +303,10 @@ class Anneal:
         g.amp_avg = sched.amp_avg
         g.smooth = sched.smooth
         g.adaptive = int(sched.adaptive)
+        g.self_cool, g.boil_blocks = int(sched.self_cool), int(sched.boil_blocks)
+        g.cool_blocks = int(sched.cool_blocks)
+        self.T_self = np.zeros(self._T.size)  # temperatures used under self-cooling (absolute)
+        g.T_self = _p(self.T_self)
         g.seed = self.seed
         g.trace_k0 = g.trace_k1 = 0
         g.band = 1e-12

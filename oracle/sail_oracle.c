@@ -403,6 +403,15 @@ typedef struct {
      * the branching fraction and the imprint strength are scaled by the
      * population mean of the running acceptance rate (which starts at 1) */
     int adaptive;
+    /* self-cooling (Sec. 2.4).  Reading: the temperature of block b (all its
+     * sweeps) follows from the population's residues at the block's start:
+     * boil (b < boil_blocks) T = mean chi^2; cool (the next cool_blocks
+     * blocks) T = (1 - x) mean + x min with x = (b - boil_blocks + 1) /
+     * cool_blocks; freeze (after) T = min / (1 + j), j the freeze block
+     * count from 1.  The mean sums the walkers in order.  The temperatures
+     * used are written to T_self[k] (absolute units; n_T entries). */
+    int self_cool, boil_blocks, cool_blocks;
+    double *T_self;
 } or_anneal_args;
 
 typedef struct { int64_t near, hard, props, acc; int32_t fk, fq; } walker_log;
@@ -419,7 +428,7 @@ static void walker_sweeps(const or_anneal_args *g, int l, int k0, int k1,
     const double *omega = g->omega, *K = g->K, *w = g->w, *Ft = g->Ft;
     const uint32_t gl = g->walker_ids ? (uint32_t)g->walker_ids[l] : (uint32_t)l;
     for (int k = k0; k < k1; ++k) {
-        double Tabs = g->T[k] * g->chi2_unit;
+        double Tabs = g->self_cool ? g->T_self[k] : g->T[k] * g->chi2_unit;
         /* Eq. (amplitude-acceptance-adjustment).  Reading: the "ongoing"
          * acceptance rate is a running average over sweeps,
          *   rate <- (1 - amp_avg) rate + amp_avg (accepted / n_omega),
@@ -573,6 +582,23 @@ static int branch_event(or_anneal_args *g, int e, double *a, double *F, double *
     return st;
 }
 
+/* Self-cooling temperature of block b from the current residues. */
+static double self_cool_T(const or_anneal_args *g, int b, const double *chi2)
+{
+    double sum = 0.0, mn = chi2[0];
+    for (int l = 0; l < g->n_walkers; ++l) {
+        sum += chi2[l];
+        if (chi2[l] < mn) mn = chi2[l];
+    }
+    const double mean = sum / (double)g->n_walkers;
+    if (b < g->boil_blocks) return mean;
+    if (b < g->boil_blocks + g->cool_blocks) {
+        const double x = (double)(b - g->boil_blocks + 1) / (double)g->cool_blocks;
+        return (1.0 - x) * mean + x * mn;
+    }
+    return mn / (double)(1 + (b - g->boil_blocks - g->cool_blocks + 1));
+}
+
 /* Runs global sweeps [k0, k1).  State arrays are [walker][...] and are
  * updated in place.  After sweep k, if (k+1) % resync_every == 0 every walker
  * is resynced, and if (k+1) % branch_every == 0 branching event
@@ -584,10 +610,15 @@ int or_anneal(or_anneal_args *g, int k0, int k1, double *a, double *F, double *c
     if (k0 < 0 || k1 > g->n_T || k0 > k1) return 1;
     if (g->resync_every <= 0 || g->branch_every <= 0 || g->branch_every % g->resync_every != 0) return 1;
     if (g->walker_ids && k1 / g->branch_every > k0 / g->branch_every) return 2;
+    if (g->walker_ids && g->self_cool) return 2; /* needs the whole population */
     walker_log *lg = (walker_log *)calloc((size_t)n, sizeof(walker_log));
     for (int l = 0; l < n; ++l) { lg[l].fk = -1; lg[l].fq = -1; }
     int k = k0;
     while (k < k1) {
+        if (g->self_cool && k % g->branch_every == 0) {
+            const double Tb = self_cool_T(g, k / g->branch_every, chi2);
+            for (int q = k; q < k + g->branch_every && q < g->n_T; ++q) g->T_self[q] = Tb;
+        }
         int kend = ((k / g->resync_every) + 1) * g->resync_every;
         if (kend > k1) kend = k1;
 #pragma omp parallel

@@ -490,6 +490,35 @@ def test_adaptive_branching_scales_fraction_and_imprint_by_the_mean_rate():
         assert np.array_equal(ad.a[keep], ref.a[keep])
 
 
+def test_self_cooling_temperatures_follow_the_population():
+    """Self-cooling (Sec. 2.4, reading): block 0 boils at the mean residue,
+    which for identical starting walkers is chi^2_0 to rounding; the cooling
+    ramp ends exactly at the population minimum; freeze block j runs at the
+    minimum over 1 + j; every boiling or cooling block's temperature lies
+    between the minimum and the mean of the residues at its start; a
+    block's temperature is constant within it."""
+    wl, prob = _small_problem()
+    B, nb = 100, 6
+    T = np.ones(B * nb)
+    an = O.Anneal(prob, O.Schedule(T, self_cool=1, boil_blocks=2, cool_blocks=2), 32, 6)
+    snaps = []
+    for b in range(nb):
+        snaps.append(an.chi2.copy())
+        an.run(b * B, (b + 1) * B)
+    Ts = an.T_self.reshape(nb, B)
+    assert np.all(Ts == Ts[:, :1])
+    Tb = Ts[:, 0]
+    assert abs(Tb[0] / an.chi2_unit - 1) <= 1e-14
+    for b, c in enumerate(snaps[:4]):  # boiling and cooling blocks
+        assert c.min() * (1 - 1e-15) <= Tb[b] <= c.mean() * (1 + 1e-15)
+    np.testing.assert_allclose(Tb[:2], [snaps[0].mean(), snaps[1].mean()], rtol=1e-14)
+    np.testing.assert_allclose(Tb[2], 0.5 * snaps[2].mean() + 0.5 * snaps[2].min(), rtol=1e-14)
+    assert Tb[3] == snaps[3].min()
+    for j, b in ((1, 4), (2, 5)):
+        assert Tb[b] == snaps[b].min() / (1 + j)
+    assert an.chi2.min() < snaps[0].min()
+
+
 # --------------------------------------------------------------------------
 # Smoothing (Sec. 2.6)
 # --------------------------------------------------------------------------
