@@ -86,6 +86,15 @@ typedef struct {
                                branch_fraction and imprint_t scaled by the population mean of the
                                walkers' running acceptance rates (which start at 1); runs through
                                sail_run_schedule only */
+    int self_cool;          /* 1: self-cooling (Sec. 2.4) [0]; T is then ignored except for its length,
+                               and block b (branch_every sweeps) runs at a temperature taken from the
+                               residues at its start: the mean for b < boil_blocks, then a linear ramp
+                               from the mean to the minimum over cool_blocks blocks, then
+                               min / (1 + j) in freeze block j = 1, 2, ...; a call starts at a block
+                               boundary or inside the block the previous call started; runs through
+                               sail_run_schedule only */
+    int boil_blocks;        /* >= 0 [0] */
+    int cool_blocks;        /* >= 1 [1] */
 } sail_schedule;
 
 /* Fills *s with the defaults above and T = NULL, n_T = 0. */

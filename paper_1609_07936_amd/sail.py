@@ -34,6 +34,7 @@ class ScheduleC(ctypes.Structure):
         ("eps0", ctypes.c_double), ("amp_p", ctypes.c_double), ("amp_m", ctypes.c_int),
         ("amp_avg", ctypes.c_double), ("walk_len", ctypes.c_int), ("t_units", ctypes.c_int),
         ("smooth", ctypes.c_double), ("adaptive", ctypes.c_int),
+        ("self_cool", ctypes.c_int), ("boil_blocks", ctypes.c_int), ("cool_blocks", ctypes.c_int),
     ]
 
 
@@ -198,7 +199,7 @@ class Schedule:
 
     def __init__(self, T, branch_every=100, resync_every=100, branch_fraction=0.25, imprint_t=0.1, eps0=0.1,
                  amp_p=1.0, amp_m=2, amp_avg=0.1, walk_len=0, t_units=0, smooth=0.0,
-                 adaptive=0):
+                 adaptive=0, self_cool=0, boil_blocks=0, cool_blocks=1):
         self.T = _f64(T)
         self.c = ScheduleC()
         lib().sail_schedule_defaults(ctypes.byref(self.c))
@@ -210,6 +211,7 @@ class Schedule:
         c.walk_len, c.t_units = int(walk_len), int(t_units)
         c.smooth = float(smooth)
         c.adaptive = int(adaptive)
+        c.self_cool, c.boil_blocks, c.cool_blocks = int(self_cool), int(boil_blocks), int(cool_blocks)
 
     @property
     def n_sweeps(self) -> int:

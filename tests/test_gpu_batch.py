@@ -146,6 +146,8 @@ def test_batch_errors(S):
         batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), walk_len=2), 0, 5)
     with pytest.raises(S.SailError):  # so does smoothing
         batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), smooth=0.01), 0, 5)
+    with pytest.raises(S.SailError):  # and self-cooling
+        batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), self_cool=1), 0, 5)
     batch.run(sc, 0, 5)
     torch.cuda.synchronize()
 

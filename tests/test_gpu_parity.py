@@ -161,6 +161,36 @@ def test_adaptive_branching_lockstep(S, smooth):
     assert np.all(an.ev_status[:20] == 0) and z[-1] < z[0]  # fewer walkers branched as acceptance falls
 
 
+def test_self_cooling_lockstep(S):
+    """Self-cooling (Sec. 2.4): the small workload over 20 blocks (2 boiling,
+    5 cooling, 13 freezing), every proposal against the oracle, whose block
+    temperatures come from the same residues in the same operation order."""
+    wl = W.small_64x32()
+    _anneal_lockstep(S, wl, 64, wl.seed, wl.n_sweeps, dict(self_cool=1, boil_blocks=2, cool_blocks=5))
+
+
+def test_self_cooling_stages_and_refusal(S):
+    """A self-cooling run split inside a block continues with that block's
+    temperature (bits equal the one-call run); a run that starts inside a
+    block no earlier call on the problem started is refused."""
+    wl = W.small_64x32()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, 400)
+    sc = S.Schedule(T, self_cool=1, boil_blocks=1, cool_blocks=2)
+    one = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    one.init_walkers(32, 3)
+    one.run(sc, 0, 400)
+    two = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    two.init_walkers(32, 3)
+    two.run(sc, 0, 150)
+    two.run(sc, 150, 250)
+    np.testing.assert_array_equal(one.read_state()["a"], two.read_state()["a"])
+    np.testing.assert_array_equal(one.read_chi2(), two.read_chi2())
+    three = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    three.init_walkers(32, 3)
+    with pytest.raises(S.SailError):
+        three.run(sc, 150, 50)
+
+
 @pytest.mark.parametrize("walk_len", [1, 4])
 def test_selection_walk_lockstep(S, walk_len):
     """Sec. 2.3 index selection with a walk of independence Metropolis steps
