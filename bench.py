@@ -51,6 +51,8 @@ def parse():
                     help="fp64/fp32: smoothing amplitude of Sec. 2.6 after every branching event (paper: 0.01)")
     ap.add_argument("--adaptive", action="store_true",
                     help="fp64/fp32: adaptive branching (fraction and imprint scaled by the mean acceptance rate)")
+    ap.add_argument("--self-cool", default="",
+                    help="fp64/fp32: self-cooling of Sec. 2.4 as 'boil_blocks,cool_blocks' (blocks of 100 sweeps)")
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -395,8 +397,10 @@ def main():
         raise SystemExit("steps exceed the schedule")
     stream = torch.cuda.current_stream()
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    boil, cool = (int(x) for x in args.self_cool.split(",")) if args.self_cool else (0, 1)
     sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=wl.resync_every, smooth=args.smooth,
-                       adaptive=int(args.adaptive))
+                       adaptive=int(args.adaptive), self_cool=int(bool(args.self_cool)), boil_blocks=boil,
+                       cool_blocks=cool)
     gp.init_walkers(wl.n_walkers, wl.seed, precision=precision, stream=stream)
     for s in range(warm):
         gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
@@ -443,6 +447,7 @@ def main():
             "n_omega": int(wl.omega.size), "n_tau": int(wl.tau.size), "n_walkers": int(wl.n_walkers),
             "sweeps_timed": SWEEPS_PER_STEP * steps, "precision": "fp32 loop" if fp32 else "fp64",
             "smooth": args.smooth, "adaptive_branching": bool(args.adaptive),
+            "self_cooling_boil_cool_blocks": args.self_cool or None,
         },
         "quality": {
             "final_chi2_over_chi2_0_median": float(np.median(chi2) / gp.chi2_unit),
@@ -463,7 +468,7 @@ def main():
             "sweep_share_of_step": sweep_ms / (elapsed * 1e3),
         },
     }
-    if fp32 and steps * SWEEPS_PER_STEP == n_sweeps_total:
+    if fp32 and steps * SWEEPS_PER_STEP == n_sweeps_total and not args.self_cool:
         line["vs_fp64"] = fp64_comparison(S, W, wl, T, gp, chi2, value, stream, args.smooth, int(args.adaptive))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps,
