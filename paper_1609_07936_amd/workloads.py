@@ -35,25 +35,31 @@ def lorentzian_mass(w0: float, gamma: float, lo: float, hi: float) -> float:
 
 @dataclass
 class Target:
+    """Sum of Lorentzians on the support [lo, hi] (default the whole window
+    [0, omega_max]; Eq. lorentzian-band clips to a band), unit zeroth moment."""
     centres: np.ndarray
     widths: np.ndarray
     weights: np.ndarray
     omega_max: float
+    lo: float = 0.0
+    hi: float | None = None
 
     def __post_init__(self):
         self.centres = np.asarray(self.centres, dtype=np.float64)
         self.widths = np.asarray(self.widths, dtype=np.float64)
         self.weights = np.asarray(self.weights, dtype=np.float64)
-        mass = sum(c * lorentzian_mass(w0, g, 0.0, self.omega_max)
+        if self.hi is None:
+            self.hi = self.omega_max
+        mass = sum(c * lorentzian_mass(w0, g, self.lo, self.hi)
                    for c, w0, g in zip(self.weights, self.centres, self.widths))
-        self.norm = 1.0 / mass  # unit zeroth moment on [0, omega_max]
+        self.norm = 1.0 / mass  # unit zeroth moment on the support
 
     def density(self, w):
         w = np.asarray(w, dtype=np.float64)
         s = np.zeros_like(w)
         for c, w0, g in zip(self.weights, self.centres, self.widths):
             s = s + c * lorentzian(w, w0, g)
-        return self.norm * s * ((w >= 0.0) & (w <= self.omega_max))
+        return self.norm * s * ((w >= self.lo) & (w <= self.hi))
 
 
 def simpson_weights(n_intervals: int, h: float) -> np.ndarray:
@@ -66,10 +72,10 @@ def simpson_weights(n_intervals: int, h: float) -> np.ndarray:
 
 
 def transform_quadrature(target: Target, tau, n_intervals: int = 100_000):
-    """F(tau_i), m0 = int S, m1 = int omega S by composite Simpson on [0, omega_max]."""
+    """F(tau_i), m0 = int S, m1 = int omega S by composite Simpson on the support [lo, hi]."""
     tau = np.asarray(tau, dtype=np.float64)
-    h = target.omega_max / n_intervals
-    x = np.linspace(0.0, target.omega_max, n_intervals + 1)
+    h = (target.hi - target.lo) / n_intervals
+    x = np.linspace(target.lo, target.hi, n_intervals + 1)
     wq = simpson_weights(n_intervals, h) * target.density(x)
     F = np.array([np.dot(wq, np.exp(-x * t)) for t in tau]) / TWO_PI
     m0 = float(np.sum(wq))
@@ -182,3 +188,76 @@ def geometric_schedule(t_hi: float, t_lo: float, n_sweeps: int) -> np.ndarray:
         return np.array([t_hi])
     k = np.arange(n_sweeps, dtype=np.float64)
     return t_hi * (t_lo / t_hi) ** (k / (n_sweeps - 1))
+
+
+def resampled_data(target: Target, tau, n_seq: int, seed: int, n_quad: int = 100_000, chunk: int = 4096):
+    """Correlation data with undersampling noise (Sec. 5.1): draw n_seq
+    stationary Gaussian sequences on the uniform lag grid whose covariance is
+    the exact F(|i - j| d_tau), and estimate F at each lag of tau as the
+    sample autocorrelation of the set.  Reading: a sequence holds 2 N_tau
+    points, each sequence's estimate averages over all origins, and sigma is
+    the standard error of the mean over sequences.  tau must start at 0.
+    Returns (F_true, F_estimate, sigma, m0, m1)."""
+    tau = np.asarray(tau, dtype=np.float64)
+    n_tau = tau.size
+    dt = tau[1] - tau[0]
+    if abs(tau[0]) > 1e-15 or not np.allclose(np.diff(tau), dt, rtol=1e-12, atol=0):
+        raise ValueError("resampled data need a uniform tau grid starting at 0")
+    L = 2 * n_tau
+    lags = dt * np.arange(L)
+    Fl, m0, m1 = transform_quadrature(target, lags, n_quad)
+    C = Fl[np.abs(np.arange(L)[:, None] - np.arange(L)[None, :])]
+    lam, V = np.linalg.eigh(C)
+    A = V * np.sqrt(np.clip(lam, 0.0, None))  # C = A A^T (negative rounding eigenvalues clipped)
+    rng = np.random.default_rng(seed)
+    counts = (L - np.arange(n_tau)).astype(np.float64)
+    s1 = np.zeros(n_tau)
+    s2 = np.zeros(n_tau)
+    done = 0
+    while done < n_seq:
+        m = min(chunk, n_seq - done)
+        X = rng.standard_normal((m, L)) @ A.T
+        Xf = np.fft.rfft(X, 2 * L, axis=1)
+        r = np.fft.irfft(Xf * np.conj(Xf), 2 * L, axis=1)[:, :n_tau] / counts
+        s1 += r.sum(axis=0)
+        s2 += (r * r).sum(axis=0)
+        done += m
+    est = s1 / n_seq
+    var = np.maximum(s2 / n_seq - est * est, 0.0)
+    sigma = np.sqrt(var / n_seq)
+    return Fl[:n_tau], est, sigma, m0, m1
+
+
+def paper_band(noise: str = "none", n_seq: int = 0, level: float = 0.0, seed: int = 7, n_omega: int = 1000,
+               n_tau: int = 64, d_tau: float = 0.1, n_walkers: int = 1500, n_sweeps: int = 20000) -> Workload:
+    """The paper's model (Eq. lorentzian-band): L(omega; 1, 1) + L(omega; 2, 1)
+    clipped to [0.5, 2.5], n_omega bins on [0, 3.5], 1500 walkers (Sec. 5.3).
+    The tau grid is a reading (the paper does not give it): n_tau uniform
+    points from 0 in steps of d_tau.  noise: "none" (exact data, unweighted
+    residue), "iid" (sigma = level F), or "resampled" (the Sec. 5.1 generator
+    with n_seq sequences).  Blocks of 100 sweeps."""
+    tgt = Target([1.0, 2.0], [1.0, 1.0], [1.0, 1.0], 3.5, lo=0.5, hi=2.5)
+    omega = bin_centres(3.5, n_omega)
+    tau = d_tau * np.arange(n_tau, dtype=np.float64)
+    if noise == "resampled":
+        F, Ft, sigma, m0, m1 = resampled_data(tgt, tau, n_seq, seed)
+    else:
+        F, m0, m1 = transform_quadrature(tgt, tau)
+        if noise == "iid":
+            rng = np.random.default_rng(seed)
+            sigma = level * F
+            Ft = F + sigma * rng.standard_normal(F.size)
+        elif noise == "none":
+            Ft, sigma = F.copy(), None
+        else:
+            raise ValueError(f"unknown noise model {noise!r}")
+    return Workload(f"band-{noise}", omega, tau, F, Ft, sigma, m0, m1, tgt, n_walkers, n_sweeps, 1.0, 1.0, 100, 100,
+                    seed)
+
+
+def band_skew(spectrum, omega, omega_m: float = 1.5) -> float:
+    """The skew of Sec. 5.3: |int_0^omega_m S - int_omega_m^inf S| / int S, the
+    bins split by whether their centre lies below omega_m."""
+    a = np.asarray(spectrum, dtype=np.float64)
+    left = a[np.asarray(omega) < omega_m].sum()
+    return float(abs(left - (a.sum() - left)) / a.sum())
