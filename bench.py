@@ -31,7 +31,7 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector
 SWEEPS_PER_STEP = 100
 # workload -> stem of its sweep-kernel summaries under profiles/
 WORKLOADS = {"fp64": "k_sweep_fp64_512x128x16384", "fp32": "k_sweep_fp32_512x128x16384",
-             "batched": "k_sweep_batched_fp32_256jobs", "served": None}
+             "batched": "k_sweep_batched_fp32_256jobs", "served": None, "band": None}
 
 
 def parse():
@@ -42,7 +42,13 @@ def parse():
     ap.add_argument("--workload", default="fp64", choices=list(WORKLOADS),
                     help="fp64: 512 x 128 x 16384 walkers, FP64 loop (default); fp32: the same with the FP32 loop "
                          "and FP64 resync every 50 sweeps; batched: 256 mixed-size FP32 jobs in shared launches "
-                         "(a step is one round of 50 sweeps); served: Poisson stream of such jobs into the server")
+                         "(a step is one round of 50 sweeps); served: Poisson stream of such jobs into the server; "
+                         "band: the paper's Lorentzian band with its protocol (self-cooling, smoothing, adaptive "
+                         "branching), reporting the skew")
+    ap.add_argument("--band-noise", default="none", choices=["none", "iid", "resampled"],
+                    help="band: exact data, iid noise of --level, or the resampled generator with --n-seq sequences")
+    ap.add_argument("--level", type=float, default=1e-4, help="band: iid noise level")
+    ap.add_argument("--n-seq", type=int, default=20000, help="band: sequences of the resampled generator")
     ap.add_argument("--rate", type=float, default=50.0, help="served: offered load, jobs/s")
     ap.add_argument("--duration", type=float, default=30.0, help="served: arrival window, s")
     ap.add_argument("--max-jobs", type=int, default=256, help="served: in-flight jobs at most")
@@ -371,6 +377,76 @@ def served(args):
     print(json.dumps(line), flush=True)
 
 
+def band(args):
+    """The paper's model (Eq. lorentzian-band) with its protocol: self-cooling
+    (20 boiling and 100 cooling blocks of 100 sweeps, then freeze-out),
+    smoothing 0.01 and adaptive branching, 1500 walkers, 1000 bins; reports
+    proposals/s, the skew of Sec. 5.3 and the recovered peak positions."""
+    import torch
+    from paper_1609_07936_amd import sail as S
+    from paper_1609_07936_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = W.paper_band(args.band_noise, n_seq=args.n_seq, level=args.level)
+    blocks = wl.n_sweeps // SWEEPS_PER_STEP
+    steps = min(args.steps, blocks)
+    stream = torch.cuda.current_stream()
+    sched = S.Schedule(np.ones(wl.n_sweeps), branch_every=SWEEPS_PER_STEP, resync_every=SWEEPS_PER_STEP,
+                       smooth=0.01, adaptive=1, self_cool=1, boil_blocks=20, cool_blocks=100)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
+    gp.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sweep_ms, launches = gp.sweep_timing(reset=True)
+    proposals = wl.n_walkers * wl.omega.size * SWEEPS_PER_STEP * steps
+    spec = gp.read_spectrum(stream=stream)
+    chi2 = gp.read_chi2(stream=stream)
+    left, right = wl.omega < 1.5, wl.omega >= 1.5
+    flops = 8.0 * wl.tau.size * proposals
+    achieved = flops / (sweep_ms * 1e-3) / 1e12
+    line = {
+        "metric": "walker proposals/s at matched final chi2",
+        "value": proposals / elapsed,
+        "unit": "proposals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "paper's two-peak Lorentzian band: L(1, 1) + L(2, 1) clipped to [0.5, 2.5], 1000 bins on "
+                        f"[0, 3.5], {wl.tau.size} tau from 0 step {wl.tau[1]:g}, {wl.n_walkers} walkers, "
+                        f"{SWEEPS_PER_STEP * steps} sweeps, self-cooling (20 boil + 100 cool blocks of 100 sweeps), "
+                        "smoothing 0.01, adaptive branching",
+            "noise": args.band_noise, "level": args.level if args.band_noise == "iid" else None,
+            "n_seq": args.n_seq if args.band_noise == "resampled" else None,
+            "relative_sigma_tau0": None if wl.sigma is None else float(wl.sigma[0] / wl.F_true[0]),
+        },
+        "quality": {
+            "skew": W.band_skew(spec, wl.omega),
+            "paper_skew_noiseless_1e-5_1e-4": [0.004, 0.017, 0.05],
+            "peaks": [float(wl.omega[left][np.argmax(spec[left])]), float(wl.omega[right][np.argmax(spec[right])])],
+            "final_chi2_over_chi2_0_median": float(np.median(chi2) / gp.chi2_unit),
+            "at_sweep": SWEEPS_PER_STEP * steps,
+        },
+        "roofline": {"kernel": "k_sweep<double>", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "avg_launch_ms": sweep_ms / launches, "launches": launches,
+                     "sweep_share_of_step": sweep_ms / (elapsed * 1e3)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -381,6 +457,8 @@ def main():
         return batched(args)
     if args.workload == "served":
         return served(args)
+    if args.workload == "band":
+        return band(args)
     import torch
     from paper_1609_07936_amd import sail as S
     from paper_1609_07936_amd import workloads as W

@@ -191,6 +191,18 @@ def test_self_cooling_stages_and_refusal(S):
         three.run(sc, 150, 50)
 
 
+@pytest.mark.parametrize("noise", ["none", "resampled"])
+def test_paper_band_first_sweeps_lockstep(S, noise):
+    """The paper's band (1000 bins, 64 times, 1500 walkers) under its
+    protocol's schedule (self-cooling), exact data with the unweighted
+    residue and resampled data with its standard errors: the first two
+    sweeps of every walker against the oracle."""
+    wl = W.paper_band(noise, n_seq=20000)
+    _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, 2,
+                     dict(smooth=0.01, adaptive=1, self_cool=1, boil_blocks=20, cool_blocks=100),
+                     sigma=wl.sigma is not None, T=np.ones(wl.n_sweeps))
+
+
 @pytest.mark.parametrize("walk_len", [1, 4])
 def test_selection_walk_lockstep(S, walk_len):
     """Sec. 2.3 index selection with a walk of independence Metropolis steps
