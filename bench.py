@@ -395,6 +395,7 @@ def band(args):
     sched = S.Schedule(np.ones(wl.n_sweeps), branch_every=SWEEPS_PER_STEP, resync_every=SWEEPS_PER_STEP,
                        smooth=0.01, adaptive=1, self_cool=1, boil_blocks=20, cool_blocks=100)
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.autotune_layout(wl.n_walkers, S.SAIL_FP64, stream=stream)  # 1500 walkers fill few CUs: pick the lanes
     gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
     gp.set_timing(True)
     torch.cuda.synchronize()
@@ -431,6 +432,7 @@ def band(args):
             "noise": args.band_noise, "level": args.level if args.band_noise == "iid" else None,
             "n_seq": args.n_seq if args.band_noise == "resampled" else None,
             "relative_sigma_tau0": None if wl.sigma is None else float(wl.sigma[0] / wl.F_true[0]),
+            "layout_lanes_x_tau_per_lane": list(gp.layout()),
         },
         "quality": {
             "skew": W.band_skew(spec, wl.omega),
