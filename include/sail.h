@@ -81,18 +81,16 @@ typedef struct {
                                (0: off) [0]: after every branching event each walker's spectrum is
                                smoothed (a_j <- s a_{j-1} + (1 - 2s) a_j + s a_{j+1}, ends
                                (1 - s) a_end + s a_next), both sums renormalised, F and chi^2
-                               recomputed; smoothing runs through sail_run_schedule only */
+                               recomputed */
     int adaptive;           /* 1: adaptive branching (Sec. 2.5, last paragraph) [0]: each event uses
                                branch_fraction and imprint_t scaled by the population mean of the
-                               walkers' running acceptance rates (which start at 1); runs through
-                               sail_run_schedule only */
+                               walkers' running acceptance rates (which start at 1) */
     int self_cool;          /* 1: self-cooling (Sec. 2.4) [0]; T is then ignored except for its length,
                                and block b (branch_every sweeps) runs at a temperature taken from the
                                residues at its start: the mean for b < boil_blocks, then a linear ramp
                                from the mean to the minimum over cool_blocks blocks, then
                                min / (1 + j) in freeze block j = 1, 2, ...; a call starts at a block
-                               boundary or inside the block the previous call started; runs through
-                               sail_run_schedule only */
+                               boundary or inside the block the previous call started */
     int boil_blocks;        /* >= 0 [0] */
     int cool_blocks;        /* >= 1 [1] */
 } sail_schedule;

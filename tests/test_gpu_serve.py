@@ -114,3 +114,25 @@ def test_server_timeout_and_shutdown(S):
     t0 = time.perf_counter()
     srv.close()
     assert time.perf_counter() - t0 < 60
+
+
+def test_served_protocol_matches_alone(S):
+    """A served job with the paper's protocol (self-cooling, smoothing,
+    adaptive branching) beside a plain one: both equal their solo runs."""
+    jobs = W.batch_jobs(2, base_seed=6000, n_sweeps=300)
+    scheds = [S.Schedule(np.ones(300), branch_every=100, resync_every=50, smooth=0.01, adaptive=1, self_cool=1,
+                         boil_blocks=1, cool_blocks=1), _sched(S, jobs[1])]
+    srv = S.Server(hbm_bytes=2 << 30, max_jobs=4)
+    ids = [srv.submit(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1, wl.n_walkers, wl.seed, sc,
+                      precision=S.SAIL_FP64, tau_per_lane=16) for wl, sc in zip(jobs, scheds)]
+    res = [srv.wait(j, timeout=120.0) for j in ids]
+    srv.close()
+    for r, wl, sc in zip(res, jobs, scheds):
+        assert r["status"] == 0, r
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.set_tau_per_lane(16)
+        gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP64)
+        gp.run(sc, 0, 300)
+        chi2 = gp.read_chi2()
+        np.testing.assert_array_equal(r["mean_spectrum"], gp.read_spectrum())
+        assert r["chi2_min"] == chi2.min() and r["chi2_median"] == float(np.median(chi2))
