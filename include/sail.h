@@ -282,7 +282,7 @@ sail_status sail_server_wait(sail_server_t s, int64_t id, double timeout_s, sail
                              double *mean_spectrum);
 sail_status sail_server_get_stats(sail_server_t s, sail_server_stats *out);
 double sail_server_clock(sail_server_t s);
-/* Arena bytes a job takes while in flight (0 for a malformed job). */
+/* Arena bytes a job takes while in flight (0 for a malformed job or schedule). */
 size_t sail_job_footprint_bytes(const sail_job *job);
 /* Stops the thread: queued and in-flight jobs end with SAIL_ECANCELLED (after
  * the device has finished their work), then frees everything. */

@@ -92,6 +92,23 @@ def test_invalid_arguments_rejected_before_device(S):
     assert e.value.status == 1
 
 
+def test_schedule_fields_validated_on_the_host(S):
+    """The job footprint (host only) is 0 for schedules whose smoothing,
+    adaptive-branching or self-cooling fields are out of range, and positive
+    for the paper's protocol."""
+    T = np.ones(300)
+    om = (np.arange(64) + 0.5) * (10 / 64)
+    tau = 0.05 * np.arange(1, 33)
+
+    def foot(**kw):
+        return S.Server.job_footprint(om, tau, 64, S.Schedule(T, **kw), S.SAIL_FP64)
+
+    assert foot(smooth=0.01, adaptive=1, self_cool=1, boil_blocks=1, cool_blocks=1) > 0
+    for bad in (dict(smooth=0.6), dict(smooth=-0.1), dict(adaptive=2), dict(self_cool=2),
+                dict(self_cool=1, cool_blocks=0), dict(self_cool=1, boil_blocks=-1)):
+        assert foot(**bad) == 0, bad
+
+
 def test_no_device_reports_device_error(S):
     import torch
     if torch.cuda.is_available():
