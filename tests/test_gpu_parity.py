@@ -315,6 +315,41 @@ def test_large_full_size_branching_event(S):
     np.testing.assert_array_equal(st_post["a"][keep], st_pre["a"][keep])
 
 
+def test_large_full_size_protocol_event(S):
+    """The first branching event of the large workload at full size under
+    adaptive branching and smoothing (s = 0.01): the GPU's multipliers equal
+    the oracle's solve at the fraction scaled by the mean of the GPU's rates,
+    and every walker afterwards holds the renormalised smoothing of its
+    spectrum after the imprint at the scaled strength."""
+    wl = W.large_512x128()
+    n = wl.n_walkers
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    runs = {}
+    for name, be in (("plain", 10 ** 6), ("event", 100)):
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.init_walkers(n, wl.seed)
+        gp.set_event_log(True)
+        gp.run(S.Schedule(T, branch_every=be, adaptive=1, smooth=0.01), 0, 100)
+        runs[name] = (gp, gp.read_chi2(), gp.read_state())
+    chi2_pre, st_pre = runs["plain"][1], runs["plain"][2]
+    gpe, _, st_post = runs["event"]
+    ev = gpe.read_events(1, multipliers=True)
+    rho = st_pre["rate"].mean()
+    assert 0.0 < rho < 1.0
+    res = O.branch_solve(chi2_pre, O.branch_xi(wl.seed, 0, n), 0.25 * rho)
+    assert res["status"] == 0 and ev["status"][0] == 0
+    np.testing.assert_array_equal(ev["m"][0], res["m"])
+    tg, dn = O.branch_pairs(res["m"])
+    a = st_pre["a"].copy()
+    t = 0.1 * rho
+    a[tg] = t * st_pre["a"][dn] + (1 - t) * st_pre["a"][tg]
+    prob = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    rows = np.unique(np.concatenate([tg[:64], np.arange(0, n, 97)]))
+    for l in rows:
+        expect = O.renormalize(O.smooth(a[l], 0.01), wl.omega, prob.A, prob.B)
+        np.testing.assert_allclose(st_post["a"][l], expect, rtol=1e-12, atol=1e-15 * expect.max())
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_deterministic_and_stageable(S, precision):
     """Two identical runs give identical bits, and a run split in stages at
