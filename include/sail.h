@@ -62,7 +62,7 @@ typedef enum {
     SAIL_FP32 = 1  /* residual loop in FP32, resync and final residue in FP64 */
 } sail_precision;
 
-/* Annealing schedule (Sec. 3 gives the defaults noted in brackets). */
+/* Annealing schedule; defaults in brackets (those of the first fields from Sec. 3). */
 typedef struct {
     const double *T;        /* host, n_T temperatures; sweep k runs at T[k] */
     int n_T;
@@ -85,7 +85,8 @@ typedef struct {
     int adaptive;           /* 1: adaptive branching (Sec. 2.5, last paragraph) [0]: each event uses
                                branch_fraction and imprint_t scaled by the population mean of the
                                walkers' running acceptance rates (which start at 1) */
-    int self_cool;          /* 1: self-cooling (Sec. 2.4) [0]; T is then ignored except for its length,
+    int self_cool;          /* 1: self-cooling (Sec. 2.4) [0]; T then only sets the length (its values
+                               must still be positive and finite),
                                and block b (branch_every sweeps) runs at a temperature taken from the
                                residues at its start: the mean for b < boil_blocks, then a linear ramp
                                from the mean to the minimum over cool_blocks blocks, then
