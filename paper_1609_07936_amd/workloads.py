@@ -12,8 +12,8 @@ Target family (Sec. 5.2 of the paper uses a two-peak Lorentzian band):
 truncated to the model window and renormalised to unit zeroth moment.
 The transform is F(tau) = (1/2pi) int_0^omega_max S(omega) e^{-omega tau} d omega
 (Eq. transform), evaluated by composite Simpson on 1e5 intervals.
-Noise is iid Gaussian with sigma_i = level * F_i (the paper draws correlated
-noise from resampled sequences; that generator is not reproduced here).
+Noise is iid Gaussian with sigma_i = level * F_i, or, for the paper's band
+workload, the correlated undersampling noise of Sec. 5.1 (resampled_data).
 """
 from __future__ import annotations
 
