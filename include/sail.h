@@ -74,8 +74,7 @@ typedef struct {
     double amp_p;           /* p of Eq. (amplitude-acceptance-adjustment) [1] */
     int amp_m;              /* m of the same equation, integer >= 0 [2] */
     double amp_avg;         /* weight of the newest sweep in the running acceptance rate, (0, 1] [0.1] */
-    int walk_len;           /* steps of the index-selection walk of Sec. 2.3, 0..64 (0: uniform) [0];
-                               walks run through sail_run_schedule only */
+    int walk_len;           /* steps of the index-selection walk of Sec. 2.3, 0..64 (0: uniform) [0] */
     int t_units;            /* 0: T in units of the starting residue (Sec. 3); 1: absolute */
     double smooth;          /* amplitude s of the three-point smoothing stencil of Sec. 2.6, [0, 0.5]
                                (0: off) [0]: after every branching event each walker's spectrum is

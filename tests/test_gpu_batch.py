@@ -142,8 +142,6 @@ def test_batch_errors(S):
     with pytest.raises(S.SailError):
         batch.run(sc, 0, 5)
     a.set_trace(0, 0)
-    with pytest.raises(S.SailError):  # selection walks run through the single-problem path
-        batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), walk_len=2), 0, 5)
     with pytest.raises(S.SailError):  # a self-cooling run cannot start inside a block it never started
         batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), self_cool=1), 50, 5)
     batch.run(sc, 0, 5)
@@ -168,14 +166,15 @@ def test_autotune_layout(S):
 
 def test_batch_protocol_bit_identical_to_alone(S):
     """The paper's protocol in a batch: self-cooling, smoothing and adaptive
-    branching on four jobs of mixed precisions and layouts, run in two batch
-    calls split inside a block, end with the bits of the same jobs run alone
-    in one call."""
+    branching on four jobs of mixed precisions and layouts, two of them with
+    the Sec. 2.3 selection walk, run in two batch calls split inside a block,
+    end with the bits of the same jobs run alone in one call."""
     import torch
     jobs = _jobs()[:4]
     cfg = MIX[:4]
     scheds = [S.Schedule(np.ones(400), branch_every=wl.branch_every, resync_every=wl.resync_every, smooth=0.01,
-                         adaptive=1, self_cool=1, boil_blocks=1, cool_blocks=2) for wl in jobs]
+                         adaptive=1, self_cool=1, boil_blocks=1, cool_blocks=2, walk_len=2 * (i % 2))
+              for i, wl in enumerate(jobs)]
     alone = [_problem(S, wl, m[1], m[2]) for wl, m in zip(jobs, cfg)]
     mixed = [_problem(S, wl, m[1], m[2]) for wl, m in zip(jobs, cfg)]
     for gp, sc in zip(alone, scheds):

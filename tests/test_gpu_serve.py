@@ -118,10 +118,11 @@ def test_server_timeout_and_shutdown(S):
 
 def test_served_protocol_matches_alone(S):
     """A served job with the paper's protocol (self-cooling, smoothing,
-    adaptive branching) beside a plain one: both equal their solo runs."""
+    adaptive branching, a two-step selection walk) beside a plain one: both
+    equal their solo runs."""
     jobs = W.batch_jobs(2, base_seed=6000, n_sweeps=300)
     scheds = [S.Schedule(np.ones(300), branch_every=100, resync_every=50, smooth=0.01, adaptive=1, self_cool=1,
-                         boil_blocks=1, cool_blocks=1), _sched(S, jobs[1])]
+                         boil_blocks=1, cool_blocks=1, walk_len=2), _sched(S, jobs[1])]
     srv = S.Server(hbm_bytes=2 << 30, max_jobs=4)
     ids = [srv.submit(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1, wl.n_walkers, wl.seed, sc,
                       precision=S.SAIL_FP64, tau_per_lane=16) for wl, sc in zip(jobs, scheds)]
