@@ -49,6 +49,9 @@ def parse():
                     help="band: exact data, iid noise of --level, or the resampled generator with --n-seq sequences")
     ap.add_argument("--level", type=float, default=1e-4, help="band: iid noise level")
     ap.add_argument("--n-seq", type=int, default=20000, help="band: sequences of the resampled generator")
+    ap.add_argument("--band-sweeps", type=int, default=20000,
+                    help="band: length of the anneal in sweeps (the band line always runs the whole anneal)")
+    ap.add_argument("--band-cool", type=int, default=100, help="band: cooling blocks of the self-cooling schedule")
     ap.add_argument("--rate", type=float, default=50.0, help="served: offered load, jobs/s")
     ap.add_argument("--duration", type=float, default=30.0, help="served: arrival window, s")
     ap.add_argument("--max-jobs", type=int, default=256, help="served: in-flight jobs at most")
@@ -388,12 +391,12 @@ def band(args):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = W.paper_band(args.band_noise, n_seq=args.n_seq, level=args.level)
+    wl = W.paper_band(args.band_noise, n_seq=args.n_seq, level=args.level, n_sweeps=args.band_sweeps)
     blocks = wl.n_sweeps // SWEEPS_PER_STEP
-    steps = min(args.steps, blocks)
+    steps = blocks  # the skew is a property of the whole anneal
     stream = torch.cuda.current_stream()
     sched = S.Schedule(np.ones(wl.n_sweeps), branch_every=SWEEPS_PER_STEP, resync_every=SWEEPS_PER_STEP,
-                       smooth=0.01, adaptive=1, self_cool=1, boil_blocks=20, cool_blocks=100)
+                       smooth=0.01, adaptive=1, self_cool=1, boil_blocks=20, cool_blocks=args.band_cool)
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
     gp.autotune_layout(wl.n_walkers, S.SAIL_FP64, stream=stream)  # 1500 walkers fill few CUs: pick the lanes
     gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
@@ -427,7 +430,8 @@ def band(args):
         "config": {
             "workload": "paper's two-peak Lorentzian band: L(1, 1) + L(2, 1) clipped to [0.5, 2.5], 1000 bins on "
                         f"[0, 3.5], {wl.tau.size} tau from 0 step {wl.tau[1]:g}, {wl.n_walkers} walkers, "
-                        f"{SWEEPS_PER_STEP * steps} sweeps, self-cooling (20 boil + 100 cool blocks of 100 sweeps), "
+                        f"{SWEEPS_PER_STEP * steps} sweeps, self-cooling (20 boil + {args.band_cool} cool blocks of 100 "
+                        "sweeps), "
                         "smoothing 0.01, adaptive branching",
             "noise": args.band_noise, "level": args.level if args.band_noise == "iid" else None,
             "n_seq": args.n_seq if args.band_noise == "resampled" else None,
