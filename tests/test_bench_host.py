@@ -1,0 +1,33 @@
+"""Host logic of bench.py (no GPU): the traffic figure is taken from a
+profile summary only when it was measured on the sweep kernel's source as it
+stands, and more than one GPU is refused with a message."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_traffic_only_for_the_current_sweep_source(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    src = tmp_path / "paper_1609_07936_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "sail.hip").write_bytes(open(os.path.join(ROOT, "paper_1609_07936_amd", "csrc", "sail.hip"), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    stem = bench.WORKLOADS["fp64"]
+    path = tmp_path / "profiles" / f"{stem}_traffic.md"
+    assert bench.measured_traffic("fp64") is None  # no summary
+    path.write_text(f"# t\n\ntraffic_bytes_per_launch: 1.5e+11\nsweep_source_sha256_16: {bench.sweep_source_digest()}\n")
+    assert bench.measured_traffic("fp64") == 1.5e11
+    path.write_text("# t\n\ntraffic_bytes_per_launch: 1.5e+11\nsweep_source_sha256_16: 0000000000000000\n")
+    assert bench.measured_traffic("fp64") is None  # measured on another source
+    assert bench.measured_traffic("served") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
