@@ -267,6 +267,101 @@ def test_first_proposal_dchi2_exact_rational():
         assert abs(got - exact) <= 1e-13 * M, (l, got, exact, M)
 
 
+def _exact_dchi2(prob, F0, p, s, r, dp, ds):
+    """chi^2(F + dF) - chi^2(F) in exact rationals, dF = (r - 1) F + dp K_p + ds K_s."""
+    Fr = [Fraction(v) for v in F0]
+    dF = [Fraction(r - 1.0) * Fraction(F0[i]) + Fraction(dp) * Fraction(prob.K[p, i]) +
+          Fraction(ds) * Fraction(prob.K[s, i]) for i in range(F0.size)]
+    wts = [Fraction(v) for v in prob.w]
+    Ftf = [Fraction(v) for v in prob.Ft]
+    c_old = sum(w_ * (f - t) ** 2 for w_, f, t in zip(wts, Fr, Ftf))
+    c_new = sum(w_ * (f + d - t) ** 2 for w_, f, d, t in zip(wts, Fr, dF, Ftf))
+    return float(c_new - c_old)
+
+
+@pytest.mark.parametrize("amp_p,amp_m", [(1.0, 2), (0.5, 3), (1.0, 0)])
+def test_amplitude_factor_and_running_rate_exact_rational(amp_p, amp_m):
+    """Sec. 2.7, Eq. (amplitude-acceptance-adjustment): in sweep k >= 3 the
+    move width is y eps0 with y = (rate / p)^m while rate < p (else 1), and
+    the rate is the running average rate <- (1 - beta) rate + beta acc_k / N
+    over the previous sweeps (beta = 0.1, starting at 1; reading R8).  The
+    rate is rebuilt by hand from the per-sweep accept counts of the trace,
+    y and r from it and the Philox words, and the traced dchi^2 of each
+    walker's first proposal of sweep k is compared with the exact rational
+    chi^2(F + dF) - chi^2(F) on the state at the start of that sweep.  A
+    dropped or misplaced factor of y, a rate taken over the wrong window or
+    updated at the wrong time, or p and m swapped all fail here."""
+    wl, prob = _small_problem()
+    n, k_pin, beta, eps0 = 12, 12, 0.1, 0.1
+    # cold enough that a minority of moves is accepted, so the rate falls below p
+    sched = O.Schedule(np.full(20, 2e-3), amp_p=amp_p, amp_m=amp_m, amp_avg=beta, eps0=eps0,
+                       branch_every=10 ** 6, resync_every=10 ** 6)
+    an = O.Anneal(prob, sched, n, wl.seed)
+    hist = an.run(0, k_pin, trace=(0, k_pin))
+    F0 = an.F.copy()
+    rate_oracle = an.rate.copy()
+    out = an.run(k_pin, k_pin + 1, trace=(k_pin, k_pin + 1))
+    No = prob.omega.size
+    key = (wl.seed & 0xFFFFFFFF, wl.seed >> 32)
+    ys = []
+    for l in range(n):
+        rate = 1.0
+        for k in range(k_pin):
+            acc = int(np.sum(hist["accept"][l, k] & 1))
+            rate = (1.0 - beta) * rate + beta * (acc / No)
+        assert rate == rate_oracle[l]
+        y = 1.0
+        if rate < amp_p:
+            q = rate / amp_p
+            for _ in range(amp_m):
+                y = y * q
+        ys.append(y)
+        x = O.philox4x32_10((0, k_pin, l, 0), key)
+        p, s = (int(x[0]) * No) >> 32, (int(x[1]) * No) >> 32
+        r = 1.0 - y * eps0 * (2.0 * float(O.u01(x[2])) - 1.0)
+        dp, ds = O.move_deltas(prob.omega, prob.A, prob.B, p, s, r)
+        exact = _exact_dchi2(prob, F0[l], p, s, r, dp, ds)
+        got, M = out["dchi2"][l, 0, 0], out["cond"][l, 0, 0]
+        assert abs(got - exact) <= 1e-13 * M, (l, got, exact, M, y)
+    ys = np.array(ys)
+    if amp_m == 0:
+        assert np.all(ys == 1.0) and np.all(rate_oracle < amp_p)
+    else:
+        # the pin only bites where y differs from 1: most walkers must be below p
+        assert np.sum(ys < 0.9) >= n // 2, ys
+
+
+def test_init_spectrum_is_the_log_linear_max_entropy_tilt():
+    """The start spectrum is a_j = c e^{-lambda omega_j} on the bin centres:
+    log a_j + lambda omega_j is constant across the bins, and lambda is the
+    root of the tilted mean sum_j omega_j e^{-lambda omega_j} / sum_j
+    e^{-lambda omega_j} = B / A found by an independent root finder (scipy's
+    brentq on a shifted, overflow-safe form).  A tilt on the left bin edges
+    or a mean condition off by half a bin moves lambda and fails here."""
+    from scipy.optimize import brentq
+    om = W.bin_centres(10.0, 64)
+    for mu in (0.4, 1.7, 3.3, 6.1, 9.2):
+        a, lam = O.init_spectrum(om, 6.4, 6.4 * mu)
+
+        def tilted_mean(x):
+            e = np.exp(-x * (om - (om[0] if x > 0 else om[-1])))
+            return float(np.dot(om, e) / e.sum()) - mu
+
+        lam_ref = brentq(tilted_mean, -200.0, 200.0, xtol=1e-15, rtol=1e-15, maxiter=500)
+        assert abs(lam - lam_ref) <= 1e-10 * max(1.0, abs(lam_ref)), (mu, lam, lam_ref)
+        resid = np.log(a) + lam * om
+        scale = np.max(np.abs(np.log(a))) + abs(lam) * om[-1]
+        assert np.max(np.abs(resid - resid.mean())) <= 1e-13 * scale, (mu, np.ptp(resid))
+    # a planted tilt on the left edges (omega_j - d_omega / 2) in the mean condition
+    # solves a different lambda: the root finder separates the two
+    dw = om[1] - om[0]
+    a, lam = O.init_spectrum(om, 1.0, 2.0)
+    left = om - dw / 2
+    e_left = lambda x: np.exp(-x * (left - (left[0] if x > 0 else left[-1])))  # noqa: E731
+    lam_left = brentq(lambda x: float(np.dot(left, e_left(x)) / e_left(x).sum()) - 2.0, -200, 200)
+    assert abs(lam - lam_left) > 1e-3
+
+
 @pytest.mark.parametrize("walk_len", [1, 3])
 def test_selection_walk_distribution_is_exact_markov_power(walk_len):
     """Sec. 2.3 index selection: a walk of independence Metropolis steps
