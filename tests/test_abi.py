@@ -92,6 +92,19 @@ def test_invalid_arguments_rejected_before_device(S):
     assert e.value.status == 1
 
 
+def test_too_many_bins_for_one_workgroup_is_refused(S):
+    """The resync stages eight spectra per workgroup in LDS (160 KiB on
+    gfx950), which bounds N_omega at 2556: a larger grid is refused with a
+    message naming the LDS need, before any device is touched."""
+    tau = 0.05 * np.arange(1, 33)
+    F = np.exp(-tau)
+    for n in (2557, 4096):
+        om = (np.arange(n) + 0.5) * (10 / n)
+        with pytest.raises(S.SailError) as e:
+            S.Problem(om, tau, F, None, 1.0, 2.0)
+        assert e.value.status == 1 and "LDS" in str(e.value), str(e.value)
+
+
 def test_schedule_fields_validated_on_the_host(S):
     """The job footprint (host only) is 0 for schedules whose smoothing,
     adaptive-branching or self-cooling fields are out of range, and positive

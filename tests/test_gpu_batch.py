@@ -185,3 +185,34 @@ def test_batch_protocol_bit_identical_to_alone(S):
     torch.cuda.synchronize()
     for gp_a, gp_b, wl in zip(alone, mixed, jobs):
         _assert_same(_snapshot(gp_a, 4), _snapshot(gp_b, 4), wl.name)
+
+
+def test_many_jobs_reach_a_branching_boundary_together(S):
+    """256 small jobs reach a branching event in the same round with
+    smoothing and adaptive branching on, so that round stages three resync
+    descriptors and one branching descriptor per job (the largest round the
+    staging slot must hold); every job ends with the bits it has alone
+    (checked on a spread of them, in both precisions)."""
+    import torch
+    tgt = W.Target([1.2, 3.0], [0.3, 0.6], [0.5, 0.5], 6.0)
+    tau = W.uniform_tau(0.05, 1.5, 8)
+    base = W.make("many", 6.0, 16, tau, tgt, 1e-4, 21, 8, 200, 1e2, 1e-3, 100, 50, 0, n_quad=2000)
+    T = W.geometric_schedule(base.t_hi, base.t_lo, base.n_sweeps)
+    sc = S.Schedule(T, branch_every=100, resync_every=50, smooth=0.01, adaptive=1)
+    n_jobs = 256
+
+    def job(i):
+        gp = S.Problem(base.omega, base.tau, base.Ft, base.sigma, base.m0, base.m1)
+        gp.init_walkers(8, 5000 + i, precision=i % 2)
+        gp.set_event_log(True)
+        return gp
+
+    mixed = [job(i) for i in range(n_jobs)]
+    batch = S.Batch(mixed)
+    batch.run(sc, 0, base.n_sweeps)
+    torch.cuda.synchronize()
+    for i in (0, 1, 2, 63, 128, 201, 254, 255):
+        alone = job(i)
+        alone.run(sc, 0, base.n_sweeps)
+        _assert_same(_snapshot(alone, 2), _snapshot(mixed[i], 2), f"job {i}")
+        assert np.all(mixed[i].read_events(2)["status"] == 0)

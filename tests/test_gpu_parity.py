@@ -87,7 +87,26 @@ def _anneal_lockstep(S, wl, n_walkers, seed, n_sweeps, sched_kw=None, mode=0, si
     spec = gp.read_spectrum()
     dw = wl.omega[1] - wl.omega[0]
     assert np.sum(np.abs(spec - an.mean_spectrum())) * dw <= 1e-10 * wl.m0
+    _assert_untraced_twin(S, wl, n_walkers, seed, n_sweeps, gs, mode, sigma, gp, n_ev)
     return gp, an, out
+
+
+def _assert_untraced_twin(S, wl, n_walkers, seed, n_sweeps, gs, mode, sigma, gp, n_ev, precision=0):
+    """The same run without a trace window takes the kernel variant the
+    benchmark times; its state, residues and branching log equal the traced
+    (oracle-checked) run bit for bit."""
+    tw = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma if sigma else None, wl.m0, wl.m1, mode)
+    tw.init_walkers(n_walkers, seed, precision=precision)
+    tw.set_event_log(True)
+    tw.run(gs, 0, n_sweeps)
+    a, b = gp.read_state(), tw.read_state()
+    for k in ("a", "F", "rate"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=f"untraced twin: {k}")
+    np.testing.assert_array_equal(gp.read_chi2(), tw.read_chi2(), err_msg="untraced twin: chi2")
+    if n_ev:
+        ea, eb = gp.read_events(n_ev, multipliers=True), tw.read_events(n_ev, multipliers=True)
+        for k in ("delta", "pr", "z", "status", "m"):
+            np.testing.assert_array_equal(ea[k], eb[k], err_msg=f"untraced twin: events {k}")
 
 
 def test_small_full_anneal_lockstep(S):
@@ -283,6 +302,72 @@ def test_large_fp32_full_size_sampled_within_fp32_bar(S):
     np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
     st = gp.read_state()
     np.testing.assert_allclose(st["a"][ids], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_late_stage_sampled_lockstep(S, precision):
+    """The large workload at full size (16384 walkers, 512 bins, 128 times)
+    in the benchmark's launch configuration, late in the anneal: sweeps
+    0-9899 run untraced (99 blocks with their resyncs and branching events,
+    diverse spectra at low acceptance), then sweeps 9900-9902 run traced.
+    A sample of 32 walkers is loaded into the oracle from the GPU state at
+    sweep 9900 (spectra, reconstructions, residues, running rates, the
+    residue unit) and replayed proposal by proposal: dchi^2 within 1e-12 M
+    (FP64) or 1e-5 M (FP32 loop), identical accept bits apart from adopted
+    near-ties, and the sample's state after the three sweeps.  A twin
+    imported from the same checkpoint runs the three sweeps untraced and ends
+    with the same bits as the traced run."""
+    import torch
+    fp32 = precision == "fp32"
+    wl = W.large_512x128_fp32() if fp32 else W.large_512x128()
+    prec = S.SAIL_FP32 if fp32 else S.SAIL_FP64
+    n, k0, ns = wl.n_walkers, 9900, 3
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    gs = S.Schedule(T, resync_every=wl.resync_every)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(n, wl.seed, precision=prec)
+    for b in range(k0 // 100):
+        gp.run(gs, 100 * b, 100)
+    st0, chi0 = gp.read_state(), gp.read_chi2()
+    blob = gp.state_export()
+    print(f"{precision}: sweep {k0}, median chi2/chi2_0 {np.median(chi0) / gp.chi2_unit:.3e}, "
+          f"mean rate {st0['rate'].mean():.3f}", flush=True)
+    d, f = _trace_buffers(n, ns, wl.omega.size)
+    gp.set_trace(k0, k0 + ns, d.data_ptr(), f.data_ptr())
+    gp.run(gs, k0, ns)
+    torch.cuda.synchronize()
+    gp.set_trace(0, 0)
+    rng = np.random.default_rng(3)
+    ids = np.unique(np.concatenate([[0, 1, 7, 8, 4095, 16383], rng.choice(n, 26, replace=False)]))
+    g_d, g_f = d[ids].cpu().numpy(), f[ids].cpu().numpy()
+    del d, f
+    tw = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    tw.init_walkers(n, 1, precision=prec)
+    tw.state_import(blob)
+    tw.run(gs, k0, ns)
+    st1, st_tw = gp.read_state(), tw.read_state()
+    for key in ("a", "F", "rate"):
+        np.testing.assert_array_equal(st1[key], st_tw[key], err_msg=f"untraced twin: {key}")
+    np.testing.assert_array_equal(gp.read_chi2(), tw.read_chi2())
+    op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    an = O.Anneal(op, O.Schedule(T, resync_every=wl.resync_every), n, wl.seed, walker_ids=ids)
+    an.a[:] = st0["a"][ids]
+    an.F[:] = st0["F"][ids]
+    an.chi2[:] = chi0[ids]
+    an.rate[:] = st0["rate"][ids]
+    an.args.chi2_unit = gp.chi2_unit
+    bar = 1e-5 if fp32 else 1e-12
+    out = an.run(k0, k0 + ns, trace=(k0, k0 + ns), replay=g_f, band=bar)
+    assert out["hard_mismatch"] == 0, out["first_mismatch"]
+    err = np.abs(g_d - out["dchi2"])
+    worst = float(np.max(err / np.maximum(out["cond"], 1e-300)))
+    acc = float(np.mean(out["accept"] & 1))
+    print(f"worst |dchi2 error| / M over {err.size} proposals: {worst:.3e}; acceptance {acc:.4f}; "
+          f"near-ties {out['near_ties']}", flush=True)
+    assert np.all(err <= bar * out["cond"]), worst
+    np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
+    np.testing.assert_allclose(st1["a"][ids], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
+    np.testing.assert_allclose(st1["F"][ids], an.F, rtol=1e-5 if fp32 else 1e-12)
 
 
 def test_large_full_size_branching_event(S):
