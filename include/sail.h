@@ -139,12 +139,19 @@ double sail_chi2_unit(sail_problem_t p);
  * estimated over the walkers). */
 sail_status sail_read_spectrum(sail_problem_t p, double *out, void *stream);
 
-/* Current residue of every walker, out: host, n_walkers doubles. */
+/* Current residue chi^2 (Eq. residue, weighted by 1 / sigma_i^2 when sigma
+ * was given) of every walker, exact as of the last resync plus the summed
+ * changes of the accepted moves since; out: host, n_walkers doubles. */
 sail_status sail_read_chi2(sail_problem_t p, double *out, void *stream);
 
-/* Histogram of log10 chi^2 over [lo, hi) in n_bins bins (values outside are
- * clamped into the end bins).  If lo or hi is NaN the ensemble minimum /
- * maximum is used.  counts: host, n_bins uint64. */
+/* Histogram of log10 chi^2 over the walkers, over [lo, hi) in n_bins bins,
+ * 1 <= n_bins <= 4096 (values outside are clamped into the end bins).  A
+ * library output, not a quantity of the paper: it summarises the spread of
+ * the population's residues between its mean and minimum, which drive the
+ * self-cooling prescription of Sec. 2.4 (residues in the unit of Sec. 3).
+ * If lo or hi is NaN the ensemble minimum / maximum is used.
+ * counts: host, n_bins uint64.  Allocates and frees a device buffer for the
+ * counts on every call. */
 sail_status sail_read_chi2_hist(sail_problem_t p, int n_bins, double lo, double hi, uint64_t *counts,
                                 void *stream);
 
