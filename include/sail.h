@@ -155,6 +155,20 @@ sail_status sail_read_chi2(sail_problem_t p, double *out, void *stream);
 sail_status sail_read_chi2_hist(sail_problem_t p, int n_bins, double lo, double hi, uint64_t *counts,
                                 void *stream);
 
+/* The same histogram for callers that cannot allocate device memory (code
+ * recorded under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): identical arguments and results, but the call makes no
+ * hipMalloc / hipFree or other allocating call.  Its scratch (the range and
+ * the counts) is a device-resident array inside the library, one per device,
+ * held until the process ends; its first call on a device looks up that
+ * device's copy.  n_bins above 4096 (the array's size) is SAIL_EINVAL.
+ * counts: host or device memory, n_bins uint64, written by a copy on
+ * `stream`, which the call synchronises.  Every call on one device shares
+ * that device's array: calls that overlap on one device (other threads or
+ * streams) race and must be serialised by the caller. */
+sail_status sail_read_chi2_hist_noalloc(sail_problem_t p, int n_bins, double lo, double hi, uint64_t *counts,
+                                        void *stream);
+
 /* Walker state, every pointer host and optional (NULL skips it):
  *   a     [n_walkers][n_omega] spectra a_j (scale folded in)
  *   F     [n_walkers][n_tau] reconstructions F(tau_i)

@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
     L.sail_read_chi2.restype = st
     L.sail_read_chi2_hist.argtypes = [P, I, D, D, P, P]
     L.sail_read_chi2_hist.restype = st
+    L.sail_read_chi2_hist_noalloc.argtypes = [P, I, D, D, P, P]
+    L.sail_read_chi2_hist_noalloc.restype = st
     L.sail_read_state.argtypes = [P, P, P, P, P]
     L.sail_read_state.restype = st
     L.sail_read_events.argtypes = [P, I, P, P, P, P, P]
@@ -272,6 +274,17 @@ class Problem:
         out = np.zeros(n_bins, dtype=np.uint64)
         _check(lib().sail_read_chi2_hist(self._h, int(n_bins), float(lo), float(hi), _p(out),
                                          _stream_handle(stream)), "sail_read_chi2_hist")
+        return out
+
+    def read_chi2_hist_noalloc(self, n_bins: int = 64, lo: float = float("nan"), hi: float = float("nan"),
+                               out_ptr: int | None = None, stream=None) -> np.ndarray | None:
+        """The histogram through the entry point that allocates no device
+        memory.  With out_ptr (an address of n_bins uint64, host or device)
+        the counts go there and None is returned."""
+        out = None if out_ptr is not None else np.zeros(n_bins, dtype=np.uint64)
+        dst = ctypes.c_void_p(out_ptr) if out_ptr is not None else _p(out)
+        _check(lib().sail_read_chi2_hist_noalloc(self._h, int(n_bins), float(lo), float(hi), dst,
+                                                 _stream_handle(stream)), "sail_read_chi2_hist_noalloc")
         return out
 
     def read_state(self, stream=None) -> dict:
