@@ -21,21 +21,25 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sail_oracle.c")
-_LIB = os.path.join(_HERE, "libsail_oracle.so")
+# SAIL_ORACLE_LIB names another build of the same source (the sanitizer run)
+_LIB = os.environ.get("SAIL_ORACLE_LIB") or os.path.join(_HERE, "libsail_oracle.so")
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 POINT = 0
 BIN_EXACT = 1
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, OpenMP across walkers only)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP across walkers only);
+    sanitize adds AddressSanitizer and UndefinedBehaviorSanitizer."""
+    lib_path = out or _LIB
+    if force or not os.path.exists(lib_path):
+        tmp = lib_path + ".tmp"
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c11",
-               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+               "-shared", "-fPIC", *(SANITIZE_FLAGS if sanitize else []), "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 _lib = None
@@ -77,7 +81,18 @@ class AnnealArgs(ctypes.Structure):
         ("smooth", ctypes.c_double), ("adaptive", ctypes.c_int),
         ("self_cool", ctypes.c_int), ("boil_blocks", ctypes.c_int), ("cool_blocks", ctypes.c_int),
         ("T_self", ctypes.c_void_p),
+        ("ev_gap", ctypes.c_void_p), ("ev_bracket", ctypes.c_void_p), ("ev_robust", ctypes.c_void_p),
+        ("replay_m", ctypes.c_void_p), ("replay_m_events", ctypes.c_int),
+        ("branch_band", ctypes.c_double),
+        ("n_branch_near_ties", ctypes.c_int64), ("n_branch_hard", ctypes.c_int64),
+        ("first_branch_mismatch", ctypes.c_int32),
     ]
+
+# Relative perturbation of the residues against which a branching event's
+# outcome must be robust (the bar to which two sides' residues agree at an
+# event).  An event whose multipliers change under such a perturbation is a
+# branching near-tie; at every other event the multipliers must agree exactly.
+BRANCH_BAND = 1e-9
 
 
 def _declare(L: ctypes.CDLL) -> None:
@@ -92,7 +107,9 @@ def _declare(L: ctypes.CDLL) -> None:
     L.or_smooth.argtypes = [P, ctypes.c_int, ctypes.c_double]
     L.or_init_spectrum.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P]
     L.or_init_spectrum.restype = ctypes.c_int
-    L.or_branch_solve.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P, P]
+    L.or_branch_solve.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P, P, P, P, P]
+    L.or_branch_robust.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_int, P, ctypes.c_double]
+    L.or_branch_robust.restype = ctypes.c_int
     L.or_branch_solve.restype = ctypes.c_int
     L.or_branch_pairs.argtypes = [ctypes.c_int, P, P, P]
     L.or_branch_pairs.restype = ctypes.c_int
@@ -176,9 +193,22 @@ def branch_solve(chi2_values, xi, fraction: float) -> dict:
     m = np.zeros(n, dtype=np.int32)
     delta, pr = ctypes.c_double(), ctypes.c_double()
     z, tie = ctypes.c_int(), ctypes.c_int()
+    gap, bracket = ctypes.c_double(), ctypes.c_double()
     st = lib().or_branch_solve(n, _p(c), _p(x), float(fraction), ctypes.byref(delta), ctypes.byref(pr),
-                               _p(m), ctypes.byref(z), ctypes.byref(tie))
-    return {"status": st, "delta": delta.value, "pr": pr.value, "m": m, "z": z.value, "tie": tie.value}
+                               _p(m), ctypes.byref(z), ctypes.byref(tie), ctypes.byref(gap), ctypes.byref(bracket))
+    st_eff = 2 if (st == 0 and tie.value) else st
+    robust = lib().or_branch_robust(n, _p(c), _p(x), float(fraction), st_eff,
+                                    _p(m if st_eff == 0 else np.ones(n, dtype=np.int32)), BRANCH_BAND)
+    return {"status": st, "delta": delta.value, "pr": pr.value, "m": m, "z": z.value, "tie": tie.value,
+            "gap": gap.value, "bracket": bracket.value, "robust": bool(robust)}
+
+
+def branch_robust(chi2_values, xi, fraction: float, status: int, m, eps: float) -> bool:
+    """Whether a solve ending with (status, m) keeps that outcome when the
+    residues are perturbed by eps relative in four sign patterns."""
+    c, x = _f64(chi2_values), _f64(xi)
+    mm = np.ascontiguousarray(m, dtype=np.int32)
+    return bool(lib().or_branch_robust(c.size, _p(c), _p(x), float(fraction), int(status), _p(mm), float(eps)))
 
 
 def branch_pairs(m) -> tuple[np.ndarray, np.ndarray]:
@@ -316,6 +346,11 @@ class Anneal:
         self.ev_z = np.zeros(n_ev, dtype=np.int32)
         self.ev_status = np.full(n_ev, -1, dtype=np.int32)
         self.ev_m = np.zeros((n_ev, self.n), dtype=np.int32)
+        self.ev_gap = np.full(n_ev, np.inf)
+        self.ev_bracket = np.full(n_ev, np.inf)
+        self.ev_robust = np.full(n_ev, -1, dtype=np.int32)
+        g.ev_gap, g.ev_bracket, g.ev_robust = _p(self.ev_gap), _p(self.ev_bracket), _p(self.ev_robust)
+        g.branch_band = BRANCH_BAND
         g.max_events = n_ev
         g.ev_delta, g.ev_pr, g.ev_z = _p(self.ev_delta), _p(self.ev_pr), _p(self.ev_z)
         g.ev_status, g.ev_m = _p(self.ev_status), _p(self.ev_m)
@@ -326,10 +361,22 @@ class Anneal:
         g.chi2_unit = self.chi2_unit
 
     def run(self, k0: int, k1: int, trace: tuple[int, int] | None = None, replay: np.ndarray | None = None,
-            band: float = 1e-12) -> dict:
+            band: float = 1e-12, replay_m: np.ndarray | None = None) -> dict:
+        """replay_m: multipliers of events 0.. taken elsewhere ([event][walker]);
+        at an event whose outcome is not robust to a relative perturbation
+        BRANCH_BAND of the residues they are adopted where they differ (a
+        logged branching near-tie), at any other event a difference counts as
+        a hard branching mismatch."""
         g = self.args
         No = self.prob.omega.size
         out = {}
+        rep_m = None
+        if replay_m is not None:
+            rep_m = np.ascontiguousarray(replay_m, dtype=np.int32)
+            assert rep_m.ndim == 2 and rep_m.shape[1] == self.n
+            g.replay_m, g.replay_m_events = _p(rep_m), rep_m.shape[0]
+        else:
+            g.replay_m, g.replay_m_events = None, 0
         if trace is not None:
             tk0, tk1 = trace
             shape = (self.n, tk1 - tk0, No)
@@ -355,14 +402,20 @@ class Anneal:
             g.trace_dchi2 = g.trace_cond = g.trace_accept = g.replay_accept = None
             g.trace_p = g.trace_s = None
         g.n_near_ties = g.n_hard_mismatch = g.n_proposals = g.n_accepted = 0
+        g.n_branch_near_ties = g.n_branch_hard = 0
+        g.first_branch_mismatch = -1
         rc = lib().or_anneal(ctypes.byref(g), int(k0), int(k1), _p(self.a), _p(self.F), _p(self.chi2),
                              _p(self.rate))
+        g.replay_m, g.replay_m_events = None, 0
+        del rep_m
         if rc == 2:
             raise ValueError("a walker sample cannot cross a branching event")
         if rc != 0:
             raise ValueError("or_anneal rejected its arguments")
         out.update(near_ties=g.n_near_ties, hard_mismatch=g.n_hard_mismatch, proposals=g.n_proposals,
-                   accepted=g.n_accepted, first_mismatch=tuple(g.first_mismatch))
+                   accepted=g.n_accepted, first_mismatch=tuple(g.first_mismatch),
+                   branch_near_ties=g.n_branch_near_ties, branch_hard=g.n_branch_hard,
+                   first_branch_mismatch=g.first_branch_mismatch)
         g.trace_k0 = g.trace_k1 = 0
         g.trace_dchi2 = g.trace_cond = g.trace_accept = g.replay_accept = None
         g.trace_p = g.trace_s = None

@@ -252,9 +252,12 @@ static double threshold(const double *chi2, const double *xi, int l, int k, doub
 }
 
 /* Evaluate the multipliers for a given Delta.  Returns the zero count and sets
- * *pr, m[] and *tie (1 when the n-th and (n+1)-th thresholds coincide). */
+ * *pr, m[], *tie (1 when the n-th and (n+1)-th thresholds coincide) and
+ * *gap, the distance between those two thresholds relative to the larger of
+ * their magnitudes and 1/Delta (the scale of their rounding): how far the
+ * multipliers are from changing under a perturbation of the residues. */
 static int branch_eval(int n, const double *chi2, const double *xi, double delta,
-                       or_heap_item *heap, int32_t *m, double *pr, int *tie)
+                       or_heap_item *heap, int32_t *m, double *pr, int *tie, double *gap)
 {
     int sz = 0;
     for (int l = 0; l < n; ++l) {
@@ -273,15 +276,23 @@ static int branch_eval(int n, const double *chi2, const double *xi, double delta
     double next = heap[0].th;
     *tie = (next == last);
     *pr = 0.5 * (last + next);
+    double scale = fmax(fmax(fabs(last), fabs(next)), 1.0 / delta);
+    *gap = (next - last) / scale;
     int z = 0;
     for (int l = 0; l < n; ++l) z += (m[l] == 0);
     return z;
 }
 
 /* Returns 0 on success (m[] set, sum m = n), 1 when the event is skipped
- * (target zero count unreachable or degenerate ensemble); then m[] = 1. */
+ * (target zero count unreachable or degenerate ensemble); then m[] = 1.
+ * Optional margins (NULL skips): *gap_out the threshold gap (branch_eval) at
+ * the final Delta (small by construction: the search ends just above the
+ * crossing of two thresholds that moves the zero count), *bracket_out the
+ * final bracket's relative width (hi - lo) / hi: that crossing lies within
+ * it below Delta. */
 int or_branch_solve(int n, const double *chi2, const double *xi, double fraction,
-                    double *delta_out, double *pr_out, int32_t *m, int *z_out, int *tie_out)
+                    double *delta_out, double *pr_out, int32_t *m, int *z_out, int *tie_out,
+                    double *gap_out, double *bracket_out)
 {
     int zt = (int)floor(fraction * (double)n + 0.5);
     double cmin = chi2[0], cmax = chi2[0];
@@ -291,23 +302,26 @@ int or_branch_solve(int n, const double *chi2, const double *xi, double fraction
     }
     for (int l = 0; l < n; ++l) m[l] = 1;
     *delta_out = 0.0; *pr_out = 0.0; *z_out = 0; *tie_out = 0;
+    if (gap_out) *gap_out = INFINITY;
+    if (bracket_out) *bracket_out = INFINITY;
     if (zt <= 0 || zt >= n || !(cmax > cmin) || !isfinite(cmax - cmin)) return 1;
     or_heap_item *heap = (or_heap_item *)malloc(sizeof(or_heap_item) * (size_t)(n + 1));
     int32_t *mt = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    double pr; int tie;
+    double pr, gap; int tie;
     double d0 = 1.0 / (cmax - cmin), lo, hi;
     int ok = 1;
-    if (branch_eval(n, chi2, xi, d0, heap, mt, &pr, &tie) >= zt) {
+#define EVAL(d) branch_eval(n, chi2, xi, (d), heap, mt, &pr, &tie, &gap)
+    if (EVAL(d0) >= zt) {
         hi = d0; lo = 0.5 * d0;
         int it = 0;
-        while (branch_eval(n, chi2, xi, lo, heap, mt, &pr, &tie) >= zt) {
+        while (EVAL(lo) >= zt) {
             hi = lo; lo = 0.5 * lo;
             if (++it >= 200) { ok = 0; break; }
         }
     } else {
         lo = d0; hi = 2.0 * d0;
         int it = 0;
-        while (branch_eval(n, chi2, xi, hi, heap, mt, &pr, &tie) < zt) {
+        while (EVAL(hi) < zt) {
             lo = hi; hi = 2.0 * hi;
             if (++it >= 200) { ok = 0; break; }
         }
@@ -315,15 +329,47 @@ int or_branch_solve(int n, const double *chi2, const double *xi, double fraction
     if (ok) {
         for (int it = 0; it < 30; ++it) {
             double mid = sqrt(lo * hi);
-            if (branch_eval(n, chi2, xi, mid, heap, mt, &pr, &tie) >= zt) hi = mid; else lo = mid;
+            if (EVAL(mid) >= zt) hi = mid; else lo = mid;
         }
-        int z = branch_eval(n, chi2, xi, hi, heap, mt, &pr, &tie);
+        int z = EVAL(hi);
         for (int l = 0; l < n; ++l) m[l] = mt[l];
         *delta_out = hi; *pr_out = pr; *z_out = z; *tie_out = tie;
+        if (gap_out) *gap_out = gap;
+        if (bracket_out) *bracket_out = (hi - lo) / hi;
     }
+#undef EVAL
     free(heap);
     free(mt);
     return ok ? 0 : 1;
+}
+
+/* Whether the solve's outcome (status and multipliers m_ref) survives a
+ * relative perturbation eps of the residues in four sign patterns (all up,
+ * all down, alternating, alternating reversed): 1 if every perturbed solve
+ * gives the same result.  Residues computed in another arithmetic agree with
+ * these only to some relative eps, so a solve that is not robust at that
+ * eps may legitimately end with other multipliers there (a near-tie). */
+int or_branch_robust(int n, const double *chi2, const double *xi, double fraction, int status_ref,
+                     const int32_t *m_ref, double eps)
+{
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    int32_t *m = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int same = 1;
+    for (int pat = 0; pat < 4 && same; ++pat) {
+        for (int l = 0; l < n; ++l) {
+            double sg = (pat == 0) ? 1.0 : (pat == 1) ? -1.0 : ((l & 1) ? -1.0 : 1.0) * (pat == 2 ? 1.0 : -1.0);
+            c[l] = chi2[l] * (1.0 + sg * eps);
+        }
+        double d, pr; int z, tie;
+        int st = or_branch_solve(n, c, xi, fraction, &d, &pr, m, &z, &tie, NULL, NULL);
+        if (st == 0 && tie) st = 2;
+        if (st != 0) for (int l = 0; l < n; ++l) m[l] = 1;
+        if (st != status_ref) same = 0;
+        for (int l = 0; l < n && same; ++l) same = (m[l] == m_ref[l]);
+    }
+    free(c);
+    free(m);
+    return same;
 }
 
 /* Pairing (Reading: the paper does not fix it): zero-multiplier walkers in
@@ -412,6 +458,21 @@ typedef struct {
      * used are written to T_self[k] (absolute units; n_T entries). */
     int self_cool, boil_blocks, cool_blocks;
     double *T_self;
+    /* optional branching margins per event (or_branch_solve): the threshold
+     * gap at the final Delta and the final bracket width; and whether the
+     * event is robust (or_branch_robust at branch_band) */
+    double *ev_gap, *ev_bracket;
+    int32_t *ev_robust;
+    /* optional multipliers taken elsewhere, [event][walker] for events
+     * [0, replay_m_events).  Where they differ from the oracle's own and the
+     * event is not robust to a relative perturbation branch_band of the
+     * residues (a branching near-tie), they are adopted; otherwise the oracle
+     * keeps its own and counts a hard branching mismatch. */
+    const int32_t *replay_m;
+    int replay_m_events;
+    double branch_band;
+    int64_t n_branch_near_ties, n_branch_hard;
+    int32_t first_branch_mismatch; /* event of the earliest hard branching mismatch, or -1 */
 } or_anneal_args;
 
 typedef struct { int64_t near, hard, props, acc; int32_t fk, fq; } walker_log;
@@ -557,18 +618,40 @@ static int branch_event(or_anneal_args *g, int e, double *a, double *F, double *
         fraction *= mean;
         t *= mean;
     }
-    double delta, pr; int z, tie;
-    int st = or_branch_solve(n, chi2, xi, fraction, &delta, &pr, m, &z, &tie);
+    double delta, pr, gap, bracket; int z, tie;
+    int st = or_branch_solve(n, chi2, xi, fraction, &delta, &pr, m, &z, &tie, &gap, &bracket);
     if (st == 0 && tie) st = 2; /* A tie leaves sum m = n ambiguous: skip. */
     if (st != 0) for (int l = 0; l < n; ++l) m[l] = 1;
+    int robust = -1; /* not evaluated */
+    if (g->ev_robust || g->replay_m) robust = or_branch_robust(n, chi2, xi, fraction, st, m, g->branch_band);
+    int adopted = 0;
+    if (g->replay_m && e < g->replay_m_events) {
+        const int32_t *mr = g->replay_m + (size_t)e * n;
+        int differ = 0;
+        int64_t sum = 0;
+        for (int l = 0; l < n; ++l) { differ |= (mr[l] != m[l]); sum += mr[l]; }
+        if (differ) {
+            if (!robust && sum == n) {
+                memcpy(m, mr, sizeof(int32_t) * (size_t)n);
+                adopted = 1;
+                g->n_branch_near_ties++;
+            } else {
+                g->n_branch_hard++;
+                if (g->first_branch_mismatch < 0) g->first_branch_mismatch = e;
+            }
+        }
+    }
     if (g->ev_status && e < g->max_events) {
         g->ev_status[e] = st;
         if (g->ev_delta) g->ev_delta[e] = delta;
         if (g->ev_pr) g->ev_pr[e] = pr;
         if (g->ev_z) g->ev_z[e] = z;
         if (g->ev_m) memcpy(g->ev_m + (size_t)e * n, m, sizeof(int32_t) * (size_t)n);
+        if (g->ev_gap) g->ev_gap[e] = gap;
+        if (g->ev_bracket) g->ev_bracket[e] = bracket;
+        if (g->ev_robust) g->ev_robust[e] = robust;
     }
-    if (st == 0) {
+    if (st == 0 || adopted) {
         int np = or_branch_pairs(n, m, tg, dn);
         for (int c = 0; c < np; ++c) {
             double *a1 = a + (size_t)tg[c] * No;

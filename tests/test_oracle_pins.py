@@ -505,6 +505,82 @@ def test_branch_multipliers_follow_the_paper_formula():
         assert th[n - 1] <= res["pr"] < th[n]
 
 
+def test_branch_margins_against_brute_force():
+    """The logged margins of a branching solve: the threshold gap equals the
+    distance between the n-th and (n+1)-th smallest thresholds of a brute-force
+    sort at the returned Delta, relative to the larger of their magnitudes and
+    1/Delta; the final bracket is the width 30 bisections in log Delta leave
+    from a factor-2 bracket, ln 2 / 2^30 to first order, with a zero-count step
+    inside it (the brute-force zero count at its lower end is below the
+    target); and these generic ensembles are robust: perturbing the residues
+    by 1e-9 relative leaves the multipliers unchanged, while the check
+    rejects other multipliers and a perturbation of 100% (which zeroes or
+    doubles residues)."""
+    rng = np.random.default_rng(23)
+    for n in (16, 64, 257):
+        chi2 = np.exp(rng.normal(0, 1.0, n))
+        xi = rng.uniform(0, 1, n)
+        res = O.branch_solve(chi2, xi, 0.25)
+        assert res["status"] == 0
+        d = res["delta"]
+        ks = np.arange(1, n + 2)
+        th = np.sort((chi2[:, None] + np.log(ks[None, :] - xi[:, None]) / d).ravel())
+        scale = max(abs(th[n - 1]), abs(th[n]), 1.0 / d)
+        assert abs(res["gap"] - (th[n] - th[n - 1]) / scale) <= 1e-12
+        assert res["gap"] > 0.0 and res["robust"]
+        # the check fails for other multipliers, and for a perturbation that
+        # reorders the residues
+        other = res["m"].copy()
+        i0, i1 = int(np.argmax(other)), int(np.flatnonzero(other == 0)[0])
+        other[i0] -= 1
+        other[i1] += 1
+        assert not O.branch_robust(chi2, xi, 0.25, 0, other, O.BRANCH_BAND)
+        assert not O.branch_robust(chi2, xi, 0.25, 0, res["m"], 1.0)
+        assert abs(res["bracket"] - math.log(2.0) / 2 ** 30) < 1e-3 * math.log(2.0) / 2 ** 30
+        zt = int(math.floor(0.25 * n + 0.5))
+
+        def zeros(delta):
+            t = np.sort((chi2[:, None] + np.log(ks[None, :] - xi[:, None]) / delta).ravel())
+            pr = 0.5 * (t[n - 1] + t[n])
+            m = np.floor(np.exp(-(chi2 - pr) * delta) + xi)
+            return int((m == 0).sum())
+
+        assert zeros(d) >= zt and zeros(d * (1.0 - res["bracket"])) < zt
+
+
+def test_branch_replay_rule():
+    """Multipliers taken elsewhere are adopted only at a near-tie: a planted
+    difference (one donor's extra copy moved to another walker) at an event
+    whose outcome is robust to the band's perturbation of the residues counts
+    as a hard branching mismatch and leaves the oracle's own result
+    (bit-identical to a run without replay); with the band widened to a
+    perturbation that does move the multipliers the same difference is
+    adopted as a logged near-tie and the planted multipliers are the ones
+    used."""
+    wl, prob = _small_problem()
+    sched = O.Schedule(W.geometric_schedule(1e2, 1e-3, 200))
+    ref = O.Anneal(prob, sched, 32, 4)
+    ref.run(0, 200)
+    assert np.all(ref.ev_status[:2] == 0) and np.all(ref.ev_robust[:2] == 1)
+    assert np.all(ref.ev_gap[:2] > 0) and np.all(ref.ev_bracket[:2] < 1e-9)
+    planted = ref.ev_m[:2].copy()
+    donor = int(np.argmax(planted[1]))
+    keeper = int(np.flatnonzero(planted[1] == 1)[0])
+    planted[1, donor] -= 1
+    planted[1, keeper] += 1
+    hard = O.Anneal(prob, sched, 32, 4)
+    out = hard.run(0, 200, replay_m=planted)
+    assert out["branch_hard"] == 1 and out["branch_near_ties"] == 0 and out["first_branch_mismatch"] == 1
+    np.testing.assert_array_equal(hard.ev_m[:2], ref.ev_m[:2])
+    np.testing.assert_array_equal(hard.a, ref.a)
+    wide = O.Anneal(prob, sched, 32, 4)
+    wide.args.branch_band = 0.3
+    out = wide.run(0, 200, replay_m=planted)
+    assert out["branch_hard"] == 0 and out["branch_near_ties"] == 1
+    np.testing.assert_array_equal(wide.ev_m[:2], planted)
+    assert not np.array_equal(wide.a, ref.a)
+
+
 def test_branch_multiplier_has_mean_w():
     """E[floor(w + xi)] = w for xi uniform on (0, 1) (Sec. 2.5)."""
     rng = np.random.default_rng(1)
