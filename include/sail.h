@@ -139,6 +139,25 @@ double sail_chi2_unit(sail_problem_t p);
  * estimated over the walkers). */
 sail_status sail_read_spectrum(sail_problem_t p, double *out, void *stream);
 
+/* Watchdog (failure detection) for sail_run_schedule.  With drift_bound > 0
+ * every resync inside a call checks every walker: a residue that is not
+ * finite, or (at the plain renormalising resync) a relative drift of either
+ * sum rule, |sum a - A| / A or |sum omega a - B| / B (Sec. 2.2: both are
+ * invariants of every move), above drift_bound before the renormalisation.
+ * The walker state at the call's start and after every clean resync
+ * boundary (after its branching event, if any) is kept as a snapshot on the
+ * device; when a check trips, the call still finishes its launches, then
+ * restores the last snapshot and returns SAIL_ENUMERIC: the walkers are as
+ * they were at that sweep (sail_watchdog_report gives it), and a run may be
+ * resumed from there.  drift_bound = 0 switches the watchdog off.  Needs
+ * walkers (SAIL_ESTATE before sail_walkers_init; re-initialising switches it
+ * off); the snapshot doubles the walker state's device memory.  Batches and
+ * served jobs do not run it. */
+sail_status sail_set_watchdog(sail_problem_t p, double drift_bound);
+/* Of the last sail_run_schedule call: the sweep after which a check tripped
+ * and the sweep the walkers were restored to, both -1 if none tripped. */
+sail_status sail_watchdog_report(sail_problem_t p, int *tripped_after_sweep, int *restored_to_sweep);
+
 /* Current residue chi^2 (Eq. residue, weighted by 1 / sigma_i^2 when sigma
  * was given) of every walker, exact as of the last resync plus the summed
  * changes of the accepted moves since; out: host, n_walkers doubles. */
@@ -183,6 +202,19 @@ sail_status sail_read_state(sail_problem_t p, double *a, double *F, double *rate
 sail_status sail_read_events(sail_problem_t p, int n_events, double *delta, double *pr, int32_t *z,
                              int32_t *status, int32_t *m);
 sail_status sail_set_event_log(sail_problem_t p, int keep_multipliers);
+
+/* Margins of the branching solves of events [0, n_events) (Sec. 2.5), host
+ * pointers, either may be NULL:
+ *   gap      the distance between the n-th and (n+1)-th smallest thresholds
+ *            theta_{l,k} = chi^2_l + ln(k - xi_l) / Delta at the final Delta
+ *            (P_r is their midpoint), relative to the larger of their
+ *            magnitudes and 1 / Delta; small by construction, since the
+ *            search for Delta ends just above the crossing of two thresholds
+ *            that moves the zero count
+ *   bracket  the relative width (hi - lo) / hi of the final bracket of that
+ *            search; the crossing lies inside it, below Delta
+ * Skipped events hold +infinity. */
+sail_status sail_read_event_margins(sail_problem_t p, int n_events, double *gap, double *bracket);
 
 /* Per-proposal trace of global sweeps [k0, k1) for every walker into device
  * buffers laid out [walker][sweep - k0][proposal]:
@@ -288,7 +320,11 @@ typedef struct {
     int64_t rounds;
     double sweep_ms; /* summed duration of the shared sweep launches */
     int64_t sweep_launches;
+    int64_t cancelled; /* jobs ended with SAIL_ECANCELLED (sail_server_cancel or shutdown) */
 } sail_server_stats;
+
+/* Job states reported by sail_server_poll. */
+enum { SAIL_JOB_QUEUED = 0, SAIL_JOB_RUNNING = 1, SAIL_JOB_DONE = 2 };
 
 /* Starts the server thread.  SAIL_ENOMEM if the arena cannot be allocated. */
 sail_status sail_server_create(const sail_server_config *cfg, sail_server_t *out);
@@ -301,6 +337,18 @@ sail_status sail_server_submit(sail_server_t s, const sail_job *job, int64_t *id
  * ensemble-mean spectrum, and forgets the job.  SAIL_ETIMEOUT leaves it. */
 sail_status sail_server_wait(sail_server_t s, int64_t id, double timeout_s, sail_job_result *res,
                              double *mean_spectrum);
+/* State of job `id` without waiting (thread-safe): SAIL_JOB_QUEUED,
+ * SAIL_JOB_RUNNING (admitted: in flight, or its outputs being read back) or
+ * SAIL_JOB_DONE (sail_server_wait returns at once).  SAIL_EINVAL for an id
+ * that is unknown or already waited for. */
+sail_status sail_server_poll(sail_server_t s, int64_t id, int *state);
+/* Cancels job `id` (thread-safe).  A queued job leaves the queue at once; a
+ * running job leaves the shared rounds at the next round boundary and its
+ * arena block returns once the device has finished the work already
+ * enqueued for it; either way its result has status SAIL_ECANCELLED (collect
+ * it with sail_server_wait).  SAIL_ESTATE if the job has already finished
+ * its anneal (its result stands), SAIL_EINVAL for an unknown id. */
+sail_status sail_server_cancel(sail_server_t s, int64_t id);
 sail_status sail_server_get_stats(sail_server_t s, sail_server_stats *out);
 double sail_server_clock(sail_server_t s);
 /* Arena bytes a job takes while in flight (0 for a malformed job or schedule). */

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsail.so")
 
 SAIL_K_POINT, SAIL_K_BIN_EXACT = 0, 1
+SAIL_JOB_QUEUED, SAIL_JOB_RUNNING, SAIL_JOB_DONE = 0, 1, 2
 SAIL_FP64, SAIL_FP32 = 0, 1
 
 
@@ -70,6 +71,7 @@ class ServerStatsC(ctypes.Structure):
         ("failed", ctypes.c_int64), ("queued", ctypes.c_int), ("in_flight", ctypes.c_int),
         ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
         ("rounds", ctypes.c_int64), ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int64),
+        ("cancelled", ctypes.c_int64),
     ]
 
 
@@ -109,6 +111,12 @@ def lib() -> ctypes.CDLL:
     L.sail_read_state.restype = st
     L.sail_read_events.argtypes = [P, I, P, P, P, P, P]
     L.sail_read_events.restype = st
+    L.sail_set_watchdog.argtypes = [P, D]
+    L.sail_set_watchdog.restype = st
+    L.sail_watchdog_report.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.sail_watchdog_report.restype = st
+    L.sail_read_event_margins.argtypes = [P, I, P, P]
+    L.sail_read_event_margins.restype = st
     L.sail_set_event_log.argtypes = [P, I]
     L.sail_set_event_log.restype = st
     L.sail_set_trace.argtypes = [P, I, I, P, P]
@@ -145,6 +153,10 @@ def lib() -> ctypes.CDLL:
     L.sail_server_submit.restype = st
     L.sail_server_wait.argtypes = [P, ctypes.c_int64, D, ctypes.POINTER(JobResultC), P]
     L.sail_server_wait.restype = st
+    L.sail_server_poll.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int)]
+    L.sail_server_poll.restype = st
+    L.sail_server_cancel.argtypes = [P, ctypes.c_int64]
+    L.sail_server_cancel.restype = st
     L.sail_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStatsC)]
     L.sail_server_get_stats.restype = st
     L.sail_server_clock.argtypes = [P]
@@ -294,6 +306,15 @@ class Problem:
         _check(lib().sail_read_state(self._h, _p(a), _p(F), _p(rate), _stream_handle(stream)), "sail_read_state")
         return {"a": a, "F": F, "rate": rate}
 
+    def set_watchdog(self, drift_bound: float) -> None:
+        _check(lib().sail_set_watchdog(self._h, float(drift_bound)), "sail_set_watchdog")
+
+    def watchdog_report(self) -> tuple[int, int]:
+        """(sweep after which the last call's check tripped, sweep restored to); -1, -1 if none."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sail_watchdog_report(self._h, ctypes.byref(a), ctypes.byref(b)), "sail_watchdog_report")
+        return a.value, b.value
+
     def set_event_log(self, keep_multipliers: bool) -> None:
         _check(lib().sail_set_event_log(self._h, int(bool(keep_multipliers))), "sail_set_event_log")
 
@@ -308,6 +329,9 @@ class Problem:
         out = {"delta": d, "pr": pr, "z": z, "status": stt}
         if multipliers:
             out["m"] = m
+        gap, bracket = np.zeros(n_events), np.zeros(n_events)
+        _check(lib().sail_read_event_margins(self._h, int(n_events), _p(gap), _p(bracket)), "sail_read_event_margins")
+        out["gap"], out["bracket"] = gap, bracket
         return out
 
     def set_trace(self, k0: int, k1: int, dchi2_ptr: int = 0, flags_ptr: int = 0) -> None:
@@ -400,7 +424,7 @@ class Batch:
         return ms.value, n.value
 
 
-SAIL_ETIMEOUT, SAIL_ECANCELLED = 7, 8
+SAIL_ESTATE, SAIL_ETIMEOUT, SAIL_ECANCELLED = 6, 7, 8
 AUTOTUNE = -1
 
 
@@ -459,6 +483,15 @@ class Server:
         out = {k: getattr(r, k) for k, _ in JobResultC._fields_}
         out["mean_spectrum"] = mean if r.status == 0 else None
         return out
+
+    def poll(self, job_id: int) -> int:
+        """SAIL_JOB_QUEUED, SAIL_JOB_RUNNING or SAIL_JOB_DONE, without waiting."""
+        state = ctypes.c_int()
+        _check(lib().sail_server_poll(self._h, int(job_id), ctypes.byref(state)), "sail_server_poll")
+        return state.value
+
+    def cancel(self, job_id: int) -> None:
+        _check(lib().sail_server_cancel(self._h, int(job_id)), "sail_server_cancel")
 
     def stats(self) -> dict:
         st = ServerStatsC()

@@ -122,6 +122,19 @@ def test_schedule_fields_validated_on_the_host(S):
         assert foot(**bad) == 0, bad
 
 
+def test_host_side_refusals_of_the_failure_handling_entry_points(S):
+    """Watchdog, per-job cancel and poll reject a NULL handle before touching
+    any device."""
+    L = S.lib()
+    assert L.sail_set_watchdog(None, 1e-9) == 1
+    a, b = ctypes.c_int(), ctypes.c_int()
+    assert L.sail_watchdog_report(None, ctypes.byref(a), ctypes.byref(b)) == 1
+    state = ctypes.c_int()
+    assert L.sail_server_poll(None, 1, ctypes.byref(state)) == 1
+    assert L.sail_server_cancel(None, 1) == 1
+    assert L.sail_read_event_margins(None, 1, None, None) == 1
+
+
 def test_no_device_reports_device_error(S):
     import torch
     if torch.cuda.is_available():

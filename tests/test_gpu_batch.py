@@ -139,8 +139,8 @@ def test_batch_errors(S):
     d = torch.zeros((16, 2, wl.omega.size), dtype=torch.float64, device="cuda")
     f = torch.zeros((16, 2, wl.omega.size), dtype=torch.uint8, device="cuda")
     a.set_trace(0, 2, d.data_ptr(), f.data_ptr())
-    with pytest.raises(S.SailError):
-        batch.run(sc, 0, 5)
+    with pytest.raises(S.SailError):  # traced batch sweeps take uniform index selection
+        batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), walk_len=2), 0, 5)
     a.set_trace(0, 0)
     with pytest.raises(S.SailError):  # a self-cooling run cannot start inside a block it never started
         batch.run(S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), self_cool=1), 50, 5)
@@ -216,3 +216,121 @@ def test_many_jobs_reach_a_branching_boundary_together(S):
         alone.run(sc, 0, base.n_sweeps)
         _assert_same(_snapshot(alone, 2), _snapshot(mixed[i], 2), f"job {i}")
         assert np.all(mixed[i].read_events(2)["status"] == 0)
+
+
+def _lockstep_bar(g_d, g_f, out, bar, tag):
+    """Per-proposal residue changes within bar * M and identical accept bits
+    (near-ties adopted by the oracle)."""
+    err = np.abs(g_d - out["dchi2"])
+    worst = float(np.max(err / np.maximum(out["cond"], 1e-300)))
+    print(f"{tag}: worst |dchi2 error| / M over {err.size} proposals {worst:.3e}, "
+          f"near-ties {out['near_ties']}", flush=True)
+    assert out["hard_mismatch"] == 0, (tag, out["first_mismatch"])
+    assert np.all(err <= bar * out["cond"]), (tag, worst)
+    np.testing.assert_array_equal(g_f & 1, out["accept"] & 1, err_msg=tag)
+
+
+def test_batched_jobs_against_the_oracle(S):
+    """Jobs of the batched workload's distribution (fewer walkers, so that the
+    oracle finishes in seconds) run in shared batch launches and are compared
+    with the oracle directly, not through their solo runs:
+      * two FP64 jobs (128 x 64 and 256 x 32, the second started alone and
+        joining the batch at sweep 50) traced over all 300 sweeps: every
+        proposal within 1e-12 M, identical accept bits, identical branching
+        multipliers at the three events, final residues, spectra and the
+        ensemble-mean spectrum at the anneal bars;
+      * one FP32 job (128 x 128) whose state at sweep 100 (after its first
+        event) is loaded into the oracle and replayed over the next resync
+        segment, sweeps 100-149: every proposal within 1e-5 M of the FP64
+        residue change;
+      * two untraced jobs in the same launches end with the bits they have
+        alone (the traced launch differs only by its trace stores)."""
+    import torch
+    import oracle as O
+    pool = W.batch_jobs(64, base_seed=7000, n_sweeps=300)
+
+    def pick(no, nt):
+        return next(j for j in pool if j.omega.size == no and j.tau.size == nt)
+
+    spec = [  # (workload, walkers, precision, tau per lane)
+        (pick(128, 64), 64, S.SAIL_FP64, 16), (pick(256, 32), 48, S.SAIL_FP64, 8),
+        (pick(128, 128), 128, S.SAIL_FP32, 16), (pick(512, 128), 256, S.SAIL_FP64, 16),
+        (pick(1024, 256), 256, S.SAIL_FP32, 32)]
+    scheds = [S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), branch_every=wl.branch_every,
+                         resync_every=wl.resync_every) for wl, *_ in spec]
+
+    def problem(wl, n, prec, tpl):
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.set_tau_per_lane(tpl)
+        gp.init_walkers(n, wl.seed, precision=prec)
+        gp.set_event_log(True)
+        assert gp.layout()[1] == tpl
+        return gp
+
+    gps = [problem(*s) for s in spec]
+    bufs = {}
+    for i in (0, 1):
+        wl, n = spec[i][0], spec[i][1]
+        d = torch.zeros((n, 300, wl.omega.size), dtype=torch.float64, device="cuda")
+        f = torch.zeros((n, 300, wl.omega.size), dtype=torch.uint8, device="cuda")
+        gps[i].set_trace(0, 300, d.data_ptr(), f.data_ptr())
+        bufs[i] = (d, f)
+    gps[1].run(scheds[1], 0, 50)  # alone first, then in the batch
+    batch = S.Batch(gps)
+    batch.run(scheds, [0, 50, 0, 0, 0], [100, 50, 100, 100, 100])
+    torch.cuda.synchronize()
+    st32, chi32 = gps[2].read_state(), gps[2].read_chi2()
+    wl32, n32 = spec[2][0], spec[2][1]
+    d32 = torch.zeros((n32, 50, wl32.omega.size), dtype=torch.float64, device="cuda")
+    f32 = torch.zeros((n32, 50, wl32.omega.size), dtype=torch.uint8, device="cuda")
+    gps[2].set_trace(100, 150, d32.data_ptr(), f32.data_ptr())
+    batch.run(scheds, [100, 100, 100, 100, 100], [200, 200, 50, 200, 100])
+    torch.cuda.synchronize()
+
+    # FP64 jobs: whole-anneal lockstep
+    for i in (0, 1):
+        wl, n = spec[i][0], spec[i][1]
+        tag = f"batched FP64 job {wl.omega.size}x{wl.tau.size}"
+        op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        an = O.Anneal(op, O.Schedule(scheds[i].T, branch_every=wl.branch_every, resync_every=wl.resync_every),
+                      n, wl.seed)
+        assert abs(gps[i].chi2_unit / an.chi2_unit - 1) < 1e-12
+        g_d, g_f = (t.cpu().numpy() for t in bufs[i])
+        ev = gps[i].read_events(3, multipliers=True)
+        out = an.run(0, 300, trace=(0, 300), replay=g_f, replay_m=ev["m"])
+        _lockstep_bar(g_d, g_f, out, 1e-12, tag)
+        # identical multipliers but at logged near-ties (adopted by the oracle)
+        assert out["branch_hard"] == 0, (tag, out["first_branch_mismatch"])
+        np.testing.assert_array_equal(ev["m"], an.ev_m[:3], err_msg=tag)
+        rob = an.ev_robust[:3] == 1
+        np.testing.assert_array_equal(ev["status"][rob], an.ev_status[:3][rob], err_msg=tag)
+        np.testing.assert_array_equal(ev["z"][rob], an.ev_z[:3][rob], err_msg=tag)
+        print(f"{tag}: branching near-ties {out['branch_near_ties']}", flush=True)
+        np.testing.assert_allclose(gps[i].read_chi2(), an.chi2, rtol=1e-9, err_msg=tag)
+        st = gps[i].read_state()
+        np.testing.assert_allclose(st["a"], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max(), err_msg=tag)
+        np.testing.assert_allclose(st["F"], an.F, rtol=1e-12, err_msg=tag)
+        dw = wl.omega[1] - wl.omega[0]
+        assert np.sum(np.abs(gps[i].read_spectrum() - an.mean_spectrum())) * dw <= 1e-10 * wl.m0, tag
+
+    # FP32 job: one resync segment replayed from its batched state at sweep 100
+    op = O.Problem(wl32.omega, wl32.tau, wl32.Ft, wl32.sigma, wl32.m0, wl32.m1)
+    an = O.Anneal(op, O.Schedule(scheds[2].T, branch_every=wl32.branch_every, resync_every=wl32.resync_every),
+                  n32, wl32.seed)
+    an.a[:] = st32["a"]
+    an.F[:] = st32["F"]
+    an.chi2[:] = chi32
+    an.rate[:] = st32["rate"]
+    an.args.chi2_unit = gps[2].chi2_unit
+    g_d, g_f = d32.cpu().numpy(), f32.cpu().numpy()
+    out = an.run(100, 150, trace=(100, 150), replay=g_f, band=1e-5)
+    _lockstep_bar(g_d, g_f, out, 1e-5, "batched FP32 job 128x128, sweeps 100-149")
+    st = gps[2].read_state()
+    np.testing.assert_allclose(st["a"], an.a, rtol=1e-9, atol=1e-12 * np.abs(an.a).max())
+    np.testing.assert_allclose(gps[2].read_chi2(), an.chi2, rtol=1e-9)
+
+    # untraced jobs of the traced launches equal their solo runs
+    for i, (k1, tag) in ((3, (300, "FP64 512x128")), (4, (200, "FP32 1024x256"))):
+        alone = problem(*spec[i])
+        alone.run(scheds[i], 0, k1)
+        _assert_same(_snapshot(alone, k1 // 100), _snapshot(gps[i], k1 // 100), tag)
