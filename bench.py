@@ -65,7 +65,28 @@ def parse():
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-finish", action="store_true",
+                    help="fp64/fp32: skip the untimed rest of the anneal (final chi2 then stays unmeasured)")
+    ap.add_argument("--no-precision-match", action="store_true",
+                    help="fp64: skip the untimed FP32-loop anneal on the same seeds")
     return ap.parse_args()
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), or the platform's description."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def matched(median_a: float, median_b: float, rel: float = 0.05) -> bool:
+    """Final residues match when the medians agree within rel (5%)."""
+    return abs(median_a / median_b - 1.0) <= rel
 
 
 def sweep_source_digest() -> str:
@@ -128,9 +149,41 @@ def fp64_comparison(S, W, wl, T, gp32, chi2_32, value32, stream, smooth=0.0, ada
     chi2_64 = gp.read_chi2(stream=stream)
     return {"spectrum_L1": float(np.sum(np.abs(sp32 - sp64)) * dw / wl.m0),
             "median_chi2_ratio_fp32_over_fp64": float(np.median(chi2_32) / np.median(chi2_64)),
+            "matched_final_chi2": matched(float(np.median(chi2_32)), float(np.median(chi2_64))),
             "sum_rule_drift_max_fp32": drift,
             "fp64_proposals_per_s": wl.n_walkers * wl.omega.size * wl.n_sweeps / dt,
             "speedup_fp32_over_fp64": value32 / (wl.n_walkers * wl.omega.size * wl.n_sweeps / dt)}
+
+
+def fp32_match(S, W, gp64, chi2_64, sched64, stream) -> dict:
+    """The FP32-loop path (FP64 resync and renormalisation every 50 sweeps) on
+    the same data, seeds and schedule, run untimed after the FP64 anneal:
+    its final residues against the FP64 path's (matched when the medians
+    agree within 5%) and the L1 distance of the averaged spectra."""
+    import torch
+    wl = W.large_512x128_fp32()
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP32, stream=stream)
+    c = sched64.c
+    sched = S.Schedule(sched64.T, branch_every=c.branch_every, resync_every=wl.resync_every, smooth=c.smooth,
+                       adaptive=c.adaptive, self_cool=c.self_cool, boil_blocks=c.boil_blocks,
+                       cool_blocks=c.cool_blocks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(wl.n_sweeps // SWEEPS_PER_STEP):
+        gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    chi2_32 = gp.read_chi2(stream=stream)
+    dw = wl.omega[1] - wl.omega[0]
+    l1 = float(np.sum(np.abs(gp.read_spectrum(stream=stream) - gp64.read_spectrum(stream=stream))) * dw / wl.m0)
+    m32, m64 = float(np.median(chi2_32)), float(np.median(chi2_64))
+    return {"fp32_final_chi2_over_chi2_0_median": m32 / gp.chi2_unit,
+            "fp32_final_chi2_over_chi2_0_min": float(chi2_32.min()) / gp.chi2_unit,
+            "median_final_chi2_ratio_fp32_over_fp64": m32 / m64,
+            "matched_final_chi2": matched(m32, m64),
+            "spectrum_L1_fp32_vs_fp64": l1,
+            "fp32_proposals_per_s_untimed_run": wl.n_walkers * wl.omega.size * wl.n_sweeps / dt}
 
 
 def cpu_baseline(wl, T, n_walkers, n_sweeps, one_thread_walkers=0) -> dict:
@@ -151,7 +204,7 @@ def cpu_baseline(wl, T, n_walkers, n_sweeps, one_thread_walkers=0) -> dict:
 
     threads = O.max_threads()
     nw, stride, props, dt = sample(n_walkers)
-    res = {"value": props / dt, "unit": "proposals/s", "cores": threads, "kind": "oracle",
+    res = {"value": props / dt, "unit": "proposals/s", "cores": threads, "cpu_model": cpu_model(), "kind": "oracle",
            "sample": f"{nw} of {wl.n_walkers} walkers (every {stride}th), sweeps 0-{n_sweeps - 1} of the same "
                      f"schedule (sweeps only, no resync or branching): {props} proposals in {dt:.2f} s"}
     if one_thread_walkers > 0:
@@ -269,7 +322,8 @@ def batched(args):
             n_prop = min(512, wl.n_walkers) * wl.omega.size * 400
             tot_p += n_prop
             tot_t += n_prop / cb["value"]
-        line["cpu_baseline"] = {"value": tot_p / tot_t, "unit": "proposals/s", "cores": cb["cores"], "kind": "oracle",
+        line["cpu_baseline"] = {"value": tot_p / tot_t, "unit": "proposals/s", "cores": cb["cores"],
+                                "cpu_model": cb["cpu_model"], "kind": "oracle",
                                 "sample": f"first 4 jobs, up to 512 walkers each (evenly strided), sweeps 0-399, "
                                           f"sweeps only: {tot_p} proposals in {tot_t:.2f} s"}
     print(json.dumps(line), flush=True)
@@ -499,10 +553,31 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sweep_ms, launches = gp.sweep_timing(reset=True)
+    gp.set_timing(False)
     elapsed = t1 - t0
     proposals = wl.n_walkers * wl.omega.size * SWEEPS_PER_STEP * steps
     value = proposals / elapsed
     chi2 = gp.read_chi2(stream=stream)
+    total_steps = n_sweeps_total // SWEEPS_PER_STEP
+    quality = {
+        "timed_region_chi2_over_chi2_0_median": float(np.median(chi2) / gp.chi2_unit),
+        "timed_region_chi2_over_chi2_0_min": float(chi2.min() / gp.chi2_unit),
+        "timed_region_ends_at_sweep": SWEEPS_PER_STEP * steps,
+    }
+    chi2_final = chi2 if steps == total_steps else None
+    if chi2_final is None and not args.no_finish:
+        # the rest of the same anneal, untimed, so that the final residues are measured
+        t2 = time.perf_counter()
+        for s in range(steps, total_steps):
+            gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
+        chi2_final = gp.read_chi2(stream=stream)
+        quality["untimed_rest_s"] = time.perf_counter() - t2
+    if chi2_final is not None:
+        quality.update({
+            "final_chi2_over_chi2_0_median": float(np.median(chi2_final) / gp.chi2_unit),
+            "final_chi2_over_chi2_0_min": float(chi2_final.min() / gp.chi2_unit),
+            "final_at_sweep": n_sweeps_total,
+        })
     # roofline of the sweep kernel: 8 N_tau algorithmic flops per proposal
     flops_per_launch = 8.0 * wl.tau.size * wl.n_walkers * wl.omega.size * (SWEEPS_PER_STEP * steps / launches)
     avg_ms = sweep_ms / launches
@@ -533,11 +608,7 @@ def main():
             "smooth": args.smooth, "adaptive_branching": bool(args.adaptive),
             "self_cooling_boil_cool_blocks": args.self_cool or None,
         },
-        "quality": {
-            "final_chi2_over_chi2_0_median": float(np.median(chi2) / gp.chi2_unit),
-            "final_chi2_over_chi2_0_min": float(chi2.min() / gp.chi2_unit),
-            "at_sweep": SWEEPS_PER_STEP * steps,
-        },
+        "quality": quality,
         "roofline": {
             "kernel": "k_sweep<float>" if fp32 else "k_sweep<double>",
             "bound": "alu",
@@ -552,8 +623,11 @@ def main():
             "sweep_share_of_step": sweep_ms / (elapsed * 1e3),
         },
     }
-    if fp32 and steps * SWEEPS_PER_STEP == n_sweeps_total and not args.self_cool:
-        line["vs_fp64"] = fp64_comparison(S, W, wl, T, gp, chi2, value, stream, args.smooth, int(args.adaptive))
+    if fp32 and chi2_final is not None and not args.self_cool:
+        line["vs_fp64"] = fp64_comparison(S, W, wl, T, gp, chi2_final, value, stream, args.smooth,
+                                          int(args.adaptive))
+    if not fp32 and chi2_final is not None and not args.no_precision_match:
+        line["precision_match"] = fp32_match(S, W, gp, chi2_final, sched, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps,
                                             one_thread_walkers=max(1, args.cpu_sample_walkers // 16))

@@ -31,3 +31,11 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_matched_final_chi2_and_cpu_model():
+    """Final residues count as matched when the median residues agree within
+    5%; the CPU baseline names the host's CPU model."""
+    assert bench.matched(1.04, 1.0) and bench.matched(0.96, 1.0)
+    assert not bench.matched(1.06, 1.0) and not bench.matched(0.9, 1.0)
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
