@@ -2,7 +2,7 @@
 FETCH_SIZE / WRITE_SIZE hardware counters to bytes: run it under the same
 `rocprofv3 --pmc` pass as the kernel being measured and divide.
 
-usage: python -m paper_1609_07936_amd.copy_calibration [MiB]
+usage: python3 copy_calibration.py [MiB]   (from the repository root)
 """
 import sys
 

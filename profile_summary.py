@@ -2,7 +2,7 @@
 call counts and durations (from --kernel-trace --stats runs) and, when the
 run collected them, per-dispatch PMC counter values.
 
-usage: python -m paper_1609_07936_amd.profile_summary RESULTS.db [--pmc COUNTER ...]
+usage: python3 profile_summary.py RESULTS.db [--pmc COUNTER ...]
 """
 from __future__ import annotations
 
