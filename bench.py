@@ -62,6 +62,8 @@ def parse():
                     help="fp64/fp32: adaptive branching (fraction and imprint scaled by the mean acceptance rate)")
     ap.add_argument("--self-cool", default="",
                     help="fp64/fp32: self-cooling of Sec. 2.4 as 'boil_blocks,cool_blocks' (blocks of 100 sweeps)")
+    ap.add_argument("--tpl", type=int, default=0,
+                    help="fp64/fp32: tau points per lane (0: the library's choice; FP64 8 or 16, FP32 16 or 32)")
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
     ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -69,6 +71,12 @@ def parse():
                     help="fp64/fp32: skip the untimed rest of the anneal (final chi2 then stays unmeasured)")
     ap.add_argument("--no-precision-match", action="store_true",
                     help="fp64: skip the untimed FP32-loop anneal on the same seeds")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="fp64: skip the batched and served measurements appended to the line")
+    ap.add_argument("--extras-rate", type=float, default=15.0, help="fp64 line's served measurement: jobs/s")
+    ap.add_argument("--extras-duration", type=float, default=20.0, help="fp64 line's served measurement: window, s")
+    ap.add_argument("--plain-jobs", type=int, default=4,
+                    help="batched/served: jobs solved one at a time on the plain FP64 path for comparison")
     return ap.parse_args()
 
 
@@ -216,7 +224,33 @@ def cpu_baseline(wl, T, n_walkers, n_sweeps, one_thread_walkers=0) -> dict:
     return res
 
 
+def plain_fp64_solves(S, W, jobs, scheds) -> dict:
+    """The comparison path for batches and the server: the same jobs solved
+    one at a time on the plain one-instance FP64 path (sail_run_schedule on
+    each problem alone, walkers initialised inside the clock), with their
+    final median residues."""
+    import torch
+    times, rel, prop = [], [], 0
+    for wl, sc in zip(jobs, scheds):
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.autotune_layout(wl.n_walkers, S.SAIL_FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP64)
+        gp.run(sc, 0, wl.n_sweeps)
+        chi2 = gp.read_chi2()
+        times.append(time.perf_counter() - t0)
+        rel.append(float(np.median(chi2) / gp.chi2_unit))
+        prop += wl.n_walkers * wl.omega.size * wl.n_sweeps
+    return {"jobs": len(jobs), "solve_s": times, "solves_per_s": len(times) / sum(times),
+            "proposals_per_s": prop / sum(times), "final_chi2_over_chi2_0_median": rel}
+
+
 def batched(args):
+    print(json.dumps(batched_line(args)), flush=True)
+
+
+def batched_line(args) -> dict:
     """256 independent inversions of mixed sizes (N_omega in
     {128..1024}, N_tau in {32..256}, walkers in {256, 1024, 4096}), FP32 loop
     with FP64 resync every 50 sweeps, 1000 sweeps each, branching every 100;
@@ -267,6 +301,13 @@ def batched(args):
     flops = 8.0 * sum(wl.n_walkers * wl.omega.size * wl.tau.size for wl in jobs) * swept
     achieved = flops / (sweep_ms * 1e-3) / 1e12
     rel = np.array([np.median(gp.read_chi2(stream=stream)) / gp.chi2_unit for gp in probs])
+    plain = None
+    if args.plain_jobs > 0 and steps * per_step == n_sweeps:
+        k = min(args.plain_jobs, len(jobs))
+        plain = plain_fp64_solves(S, W, jobs[:k], scheds[:k])
+        plain["median_final_chi2_ratio_batched_over_plain"] = [float(a / b) for a, b in
+                                                                zip(rel[:k], plain["final_chi2_over_chi2_0_median"])]
+        plain["matched_final_chi2"] = all(matched(a, b) for a, b in zip(rel[:k], plain["final_chi2_over_chi2_0_median"]))
     layouts = {}
     for gp in probs:
         k = "x".join(map(str, gp.layout()))
@@ -313,6 +354,10 @@ def batched(args):
         },
         "autotune_s": t_tune,
     }
+    if plain is not None:
+        line["plain_fp64_one_at_a_time"] = plain
+        line["speedup_over_plain_fp64"] = {"proposals_per_s": line["value"] / plain["proposals_per_s"],
+                                           "solves_per_s": line["jobs_per_s"] / plain["solves_per_s"]}
     if not args.no_cpu_baseline:
         # the oracle on the first four jobs, a walker sample of each, 400 sweeps
         tot_p, tot_t = 0, 0.0
@@ -326,10 +371,14 @@ def batched(args):
                                 "cpu_model": cb["cpu_model"], "kind": "oracle",
                                 "sample": f"first 4 jobs, up to 512 walkers each (evenly strided), sweeps 0-399, "
                                           f"sweeps only: {tot_p} proposals in {tot_t:.2f} s"}
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def served(args):
+    print(json.dumps(served_line(args)), flush=True)
+
+
+def served_line(args) -> dict:
     """Jobs of the batched workload's distribution (1000 sweeps each) arrive
     as a Poisson stream into the server; reports completed solves/s over the
     whole run and the submit-to-result latency percentiles, with sequential
@@ -353,17 +402,9 @@ def served(args):
         shapes.setdefault((wl.omega.size, wl.tau.size, wl.n_walkers), wl)
     for wl in shapes.values():
         S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1).autotune_layout(wl.n_walkers, S.SAIL_FP32)
-    # sequential solo solves of the first jobs
-    solo = []
-    for wl, sc in list(zip(jobs, scheds))[:3]:
-        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
-        gp.autotune_layout(wl.n_walkers, S.SAIL_FP32)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP32)
-        gp.run(sc, 0, wl.n_sweeps)
-        gp.read_chi2()
-        solo.append(time.perf_counter() - t0)
+    # the comparison: the first jobs solved one at a time on the plain FP64 path
+    k = min(max(1, args.plain_jobs), n_jobs)
+    plain = plain_fp64_solves(S, W, jobs[:k], scheds[:k])
     srv = S.Server(hbm_bytes=64 << 30, max_jobs=args.max_jobs)
     ids = [None] * n_jobs
     t_base = srv.clock()
@@ -391,6 +432,10 @@ def served(args):
     ok = [r for r in res if r["status"] == 0]
     lat = np.array([r["t_done"] - r["t_submit"] for r in ok])
     wait = np.array([r["t_admit"] - r["t_submit"] for r in ok])
+    # a sustainable load keeps latency flat over the window: compare the jobs
+    # that arrived in its first and second halves
+    sub = np.array([r["t_submit"] - t_base for r in ok])
+    first, second = lat[sub < args.duration / 2], lat[sub >= args.duration / 2]
     span = max(r["t_done"] for r in ok) - t_base
     prop = sum(wl.n_walkers * wl.omega.size * wl.n_sweeps for wl, r in zip(jobs, res) if r["status"] == 0)
     flops = 8.0 * sum(wl.n_walkers * wl.omega.size * wl.tau.size * wl.n_sweeps for wl, r in zip(jobs, res)
@@ -419,10 +464,15 @@ def served(args):
         },
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max()), "queue_wait_p50": float(np.percentile(wait, 50)),
-                      "queue_wait_p99": float(np.percentile(wait, 99))},
+                      "queue_wait_p99": float(np.percentile(wait, 99)),
+                      "p50_first_half_arrivals": float(np.percentile(first, 50)) if first.size else None,
+                      "p50_second_half_arrivals": float(np.percentile(second, 50)) if second.size else None,
+                      "p99_second_half_arrivals": float(np.percentile(second, 99)) if second.size else None},
+        "sustained": bool(first.size and second.size and np.percentile(second, 50) < 1.5 * np.percentile(first, 50)
+                          and len(ok) / span > 0.9 * args.rate),
         "proposals_per_s": prop / span,
-        "sequential_solo_solve_s": solo,
-        "sequential_solves_per_s": len(solo) / sum(solo),
+        "plain_fp64_one_at_a_time": plain,
+        "speedup_over_plain_fp64": {"solves_per_s": (len(ok) / span) / plain["solves_per_s"]},
         "failed": len(res) - len(ok),
         "quality": {"final_chi2_over_chi2_0_median_over_jobs": float(np.median(rel))},
         "roofline": {"kernel": "k_sweep_batched<float>", "bound": "alu", "achieved": achieved,
@@ -431,7 +481,12 @@ def served(args):
                      "launches": st["sweep_launches"]},
         "server": st,
     }
-    print(json.dumps(line), flush=True)
+    served_rel = {i: r["chi2_median"] / r["chi2_unit"] for i, r in enumerate(res[:k]) if r["status"] == 0}
+    plain["median_final_chi2_ratio_served_over_plain"] = [float(served_rel[i] / plain["final_chi2_over_chi2_0_median"][i])
+                                                          for i in served_rel]
+    plain["matched_final_chi2"] = all(matched(served_rel[i], plain["final_chi2_over_chi2_0_median"][i])
+                                      for i in served_rel)
+    return line
 
 
 def band(args):
@@ -507,6 +562,25 @@ def band(args):
     print(json.dumps(line), flush=True)
 
 
+def extras(args) -> dict:
+    """The batched and served workloads measured in the same run as the
+    default line, summarised: each against the same jobs solved one at a time
+    on the plain FP64 path."""
+    import copy
+    a = copy.copy(args)
+    a.steps, a.warmup, a.no_cpu_baseline = 10 ** 6, 1, True
+    b = batched_line(a)
+    a.rate, a.duration = args.extras_rate, args.extras_duration
+    v = served_line(a)
+    keep = ("metric", "value", "unit", "ms_per_step", "jobs_per_s", "roofline", "plain_fp64_one_at_a_time",
+            "speedup_over_plain_fp64", "latency_s", "sustained", "proposals_per_s", "failed", "quality")
+    out = {"batched": {k: b[k] for k in keep if k in b}, "served": {k: v[k] for k in keep if k in v}}
+    out["batched"]["workload"] = b["config"]["workload"]
+    out["served"]["workload"] = v["config"]["workload"]
+    out["served"]["roofline"] = {k: v["roofline"][k] for k in ("achieved", "frac", "avg_launch_ms")}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -539,6 +613,8 @@ def main():
     sched = S.Schedule(T, branch_every=SWEEPS_PER_STEP, resync_every=wl.resync_every, smooth=args.smooth,
                        adaptive=int(args.adaptive), self_cool=int(bool(args.self_cool)), boil_blocks=boil,
                        cool_blocks=cool)
+    if args.tpl:
+        gp.set_tau_per_lane(args.tpl)
     gp.init_walkers(wl.n_walkers, wl.seed, precision=precision, stream=stream)
     for s in range(warm):
         gp.run(sched, s * SWEEPS_PER_STEP, SWEEPS_PER_STEP, stream=stream)
@@ -607,6 +683,7 @@ def main():
             "sweeps_timed": SWEEPS_PER_STEP * steps, "precision": "fp32 loop" if fp32 else "fp64",
             "smooth": args.smooth, "adaptive_branching": bool(args.adaptive),
             "self_cooling_boil_cool_blocks": args.self_cool or None,
+            "layout_lanes_x_tau_per_lane": list(gp.layout()),
         },
         "quality": quality,
         "roofline": {
@@ -628,6 +705,8 @@ def main():
                                           int(args.adaptive))
     if not fp32 and chi2_final is not None and not args.no_precision_match:
         line["precision_match"] = fp32_match(S, W, gp, chi2_final, sched, stream)
+    if not fp32 and not args.no_extras:
+        line["extras"] = extras(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_sample_walkers, args.cpu_sample_sweeps,
                                             one_thread_walkers=max(1, args.cpu_sample_walkers // 16))

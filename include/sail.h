@@ -375,9 +375,14 @@ sail_status sail_set_tau_per_lane(sail_problem_t p, int tau_per_lane);
 /* Chooses the tau points per lane for this problem at n_walkers walkers and
  * `precision` by timing a few sweeps of each candidate layout on `stream`,
  * and requests it as sail_set_tau_per_lane does (*tau_per_lane receives it,
- * may be NULL).  Results are cached per (n_omega, n_tau, n_walkers,
- * precision) for the life of the process.  Leaves the problem without
- * walkers: call it before sail_walkers_init. */
+ * may be NULL).  The served loop tunes each new shape after the rounds
+ * already enqueued have drained, so the candidates run on an otherwise idle
+ * device.  Results are cached per (device architecture,
+ * n_omega, n_tau, n_walkers, precision) for the life of the process, and
+ * across processes when the environment variable SAIL_TUNE_CACHE names a
+ * file (read at the first lookup; each new choice is appended as one text
+ * line).  Leaves the problem without walkers: call it before
+ * sail_walkers_init. */
 sail_status sail_autotune_layout(sail_problem_t p, int n_walkers, int precision, int *tau_per_lane, void *stream);
 
 const char *sail_status_string(int status);

@@ -334,3 +334,34 @@ def test_batched_jobs_against_the_oracle(S):
         alone = problem(*spec[i])
         alone.run(scheds[i], 0, k1)
         _assert_same(_snapshot(alone, k1 // 100), _snapshot(gps[i], k1 // 100), tag)
+
+
+def test_autotune_cache_file_persists_across_processes(S, tmp_path):
+    """With SAIL_TUNE_CACHE naming a file, a layout tuned in one process is
+    appended to it as one line and a second process takes it from the file
+    without timing anything (malformed lines are ignored)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    cache.write_text("not a tuning line\nsail-tune-v1 gfx950 1 2\n")
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "import torch; torch.cuda.init()\n"
+            "from paper_1609_07936_amd import sail as S, workloads as W\n"
+            "wl = W.batch_jobs(1, base_seed=4242, n_sweeps=100)[0]\n"
+            "gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)\n"
+            "t0 = time.perf_counter(); tpl = gp.autotune_layout(wl.n_walkers, S.SAIL_FP32)\n"
+            "print(tpl, time.perf_counter() - t0, flush=True)\n") % root
+    env = dict(os.environ, SAIL_TUNE_CACHE=str(cache))
+    runs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=180)
+        assert r.returncode == 0, r.stderr[-2000:]
+        tpl, dt = r.stdout.split()
+        runs.append((int(tpl), float(dt)))
+    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.startswith("sail-tune-v1")]
+    valid = [ln for ln in lines if len(ln) == 7]
+    assert len(valid) == 1, valid  # tuned once, appended once
+    assert valid[0][1].startswith("gfx") and int(valid[0][6]) == runs[0][0] in (16, 32)
+    assert runs[1][0] == runs[0][0] and runs[1][1] < 0.05, runs
