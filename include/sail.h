@@ -158,6 +158,37 @@ sail_status sail_set_watchdog(sail_problem_t p, double drift_bound);
  * and the sweep the walkers were restored to, both -1 if none tripped. */
 sail_status sail_watchdog_report(sail_problem_t p, int *tripped_after_sweep, int *restored_to_sweep);
 
+/* Per-block log (the temperature, residue and acceptance rate the paper's
+ * program reports after each block, Sec. 4).  With capacity > 0,
+ * sail_run_schedule appends one record at every resync boundary, after the
+ * boundary's branching event if there is one, to a device ring of the last
+ * `capacity` records; one workgroup reduces the population in a fixed order,
+ * so records are deterministic.  Statistics over all walkers: */
+typedef struct {
+    int32_t sweep;     /* sweeps completed when the block ended */
+    int32_t event;     /* the boundary's branching event (index in the event log), or -1 */
+    double T;          /* absolute temperature of the block's last sweep */
+    double chi2_min;   /* residues after the resync and branching */
+    double chi2_mean;
+    double chi2_max;
+    double rate_mean;  /* running acceptance rate (Sec. 2.7), mean over walkers */
+    double drift_max;  /* largest relative sum-rule drift, max(|sum a - A| / A,
+                          |sum omega a - B| / |B|), found by the boundary's
+                          renormalising resync before it renormalised */
+} sail_block_record;
+/* capacity = 0 switches the log off.  Needs walkers (SAIL_ESTATE otherwise);
+ * every call, and sail_walkers_init, empties the log.  Device memory:
+ * capacity records of 56 bytes plus one double per walker.  Batches and
+ * served jobs do not keep it. */
+sail_status sail_set_block_log(sail_problem_t p, int capacity);
+/* Copies the newest min(max_records, records held) records, oldest first,
+ * into out (host, caller-allocated) on `stream` and synchronises it;
+ * *n_records receives how many, *n_total how many were appended since the
+ * log was switched on (either may be NULL).  SAIL_ESTATE when the log is
+ * off. */
+sail_status sail_read_block_log(sail_problem_t p, sail_block_record *out, int max_records, int *n_records,
+                                int64_t *n_total, void *stream);
+
 /* Current residue chi^2 (Eq. residue, weighted by 1 / sigma_i^2 when sigma
  * was given) of every walker, exact as of the last resync plus the summed
  * changes of the accepted moves since; out: host, n_walkers doubles. */
@@ -384,6 +415,26 @@ sail_status sail_set_tau_per_lane(sail_problem_t p, int tau_per_lane);
  * line).  Leaves the problem without walkers: call it before
  * sail_walkers_init. */
 sail_status sail_autotune_layout(sail_problem_t p, int n_walkers, int precision, int *tau_per_lane, void *stream);
+
+/* Device memory from the caller's allocator (for instance a framework's
+ * caching allocator, so the library's buffers count against its pool).
+ * alloc(bytes, device, user) returns `bytes` of device memory on `device`
+ * (the current HIP device of the calling thread), aligned to 256 bytes, or
+ * NULL when it cannot (the library call then fails with SAIL_ENOMEM).
+ * release(ptr, bytes, device, user) takes back a block that alloc returned,
+ * with the same bytes and device; the library has synchronised that device
+ * first, so no kernel still uses the block.  Both are called from the host
+ * thread that makes the library call, or from a server's loop thread, and
+ * must be safe to call from any thread.  The hook is process-wide and
+ * serves every later device allocation of problems, batches, staging
+ * buffers and server arenas; pinned host buffers and the fixed scratch
+ * array stay with HIP.  Blocks are returned to the allocator that made
+ * them, also after the hook is changed or cleared; the caller keeps the
+ * functions and `user` valid until then.  Both NULL restores hipMalloc and
+ * hipFree; exactly one NULL is SAIL_EINVAL. */
+typedef void *(*sail_alloc_fn)(size_t bytes, int device, void *user);
+typedef void (*sail_free_fn)(void *ptr, size_t bytes, int device, void *user);
+sail_status sail_set_allocator(sail_alloc_fn alloc, sail_free_fn release, void *user);
 
 const char *sail_status_string(int status);
 const char *sail_last_error(void);

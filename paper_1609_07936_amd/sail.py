@@ -65,6 +65,12 @@ class JobResultC(ctypes.Structure):
     ]
 
 
+class BlockRecordC(ctypes.Structure):
+    _fields_ = [("sweep", ctypes.c_int32), ("event", ctypes.c_int32), ("T", ctypes.c_double),
+                ("chi2_min", ctypes.c_double), ("chi2_mean", ctypes.c_double), ("chi2_max", ctypes.c_double),
+                ("rate_mean", ctypes.c_double), ("drift_max", ctypes.c_double)]
+
+
 class ServerStatsC(ctypes.Structure):
     _fields_ = [
         ("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
@@ -76,6 +82,12 @@ class ServerStatsC(ctypes.Structure):
 
 
 _lib = None
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
+# Every pair of callbacks ever installed stays referenced: blocks go back to
+# the allocator that made them, also after the hook has changed.
+_installed_hooks: list = []
 
 
 def lib() -> ctypes.CDLL:
@@ -115,6 +127,11 @@ def lib() -> ctypes.CDLL:
     L.sail_set_watchdog.restype = st
     L.sail_watchdog_report.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.sail_watchdog_report.restype = st
+    L.sail_set_block_log.argtypes = [P, I]
+    L.sail_set_block_log.restype = st
+    L.sail_read_block_log.argtypes = [P, ctypes.POINTER(BlockRecordC), I, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int64), P]
+    L.sail_read_block_log.restype = st
     L.sail_read_event_margins.argtypes = [P, I, P, P]
     L.sail_read_event_margins.restype = st
     L.sail_set_event_log.argtypes = [P, I]
@@ -165,6 +182,8 @@ def lib() -> ctypes.CDLL:
     L.sail_job_footprint_bytes.restype = ctypes.c_size_t
     L.sail_server_destroy.argtypes = [P]
     L.sail_server_destroy.restype = None
+    L.sail_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
+    L.sail_set_allocator.restype = st
     L.sail_status_string.argtypes = [I]
     L.sail_status_string.restype = ctypes.c_char_p
     L.sail_last_error.argtypes = []
@@ -201,6 +220,49 @@ def _stream_handle(stream) -> int | None:
     if isinstance(stream, int):
         return stream or None
     return int(stream.cuda_stream) or None
+
+
+def set_allocator(alloc=None, release=None) -> None:
+    """Routes the library's device allocations through alloc(bytes, device)
+    -> int address (0 or None when out of memory) and release(address, bytes,
+    device); both None restores hipMalloc/hipFree.  Process-wide."""
+    if (alloc is None) != (release is None):
+        raise ValueError("give both functions or neither")
+    if alloc is None:
+        _check(lib().sail_set_allocator(_ALLOC_FN(), _FREE_FN(), None), "sail_set_allocator")
+        return
+
+    def _a(nbytes, device, _user):
+        try:
+            return int(alloc(int(nbytes), int(device)) or 0) or None
+        except Exception:
+            return None
+
+    def _r(ptr, nbytes, device, _user):
+        release(int(ptr), int(nbytes), int(device))
+
+    pair = (_ALLOC_FN(_a), _FREE_FN(_r))
+    _installed_hooks.append(pair)
+    _check(lib().sail_set_allocator(pair[0], pair[1], None), "sail_set_allocator")
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Takes the library's device buffers from PyTorch's caching allocator
+    (enable=False goes back to hipMalloc).  Blocks are allocated on torch's
+    current stream of the device; the library synchronises the device before
+    it hands one back."""
+    if not enable:
+        set_allocator(None, None)
+        return
+    import torch
+
+    def alloc(nbytes, device):
+        return torch.cuda.caching_allocator_alloc(nbytes, device=device)
+
+    def release(ptr, _nbytes, _device):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    set_allocator(alloc, release)
 
 
 def footprint_bytes(n_omega: int, n_tau: int, n_walkers: int, precision: int = SAIL_FP64) -> int:
@@ -314,6 +376,27 @@ class Problem:
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(lib().sail_watchdog_report(self._h, ctypes.byref(a), ctypes.byref(b)), "sail_watchdog_report")
         return a.value, b.value
+
+    def set_block_log(self, capacity: int) -> None:
+        _check(lib().sail_set_block_log(self._h, int(capacity)), "sail_set_block_log")
+
+    def read_block_log(self, max_records: int = 1 << 20, stream=None) -> dict:
+        """The newest records of the per-block log, oldest first, as arrays
+        keyed by field, plus 'total' (records appended since the log was
+        switched on)."""
+        n = ctypes.c_int()
+        total = ctypes.c_int64()
+        probe = (BlockRecordC * 1)()
+        _check(lib().sail_read_block_log(self._h, probe, 0, ctypes.byref(n), ctypes.byref(total),
+                                         _stream_handle(stream)), "sail_read_block_log")
+        m = int(min(max_records, total.value))
+        buf = (BlockRecordC * max(m, 1))()
+        _check(lib().sail_read_block_log(self._h, buf, m, ctypes.byref(n), ctypes.byref(total),
+                                         _stream_handle(stream)), "sail_read_block_log")
+        recs = buf[:n.value]
+        out = {f: np.array([getattr(r, f) for r in recs]) for f, _ in BlockRecordC._fields_}
+        out["total"] = total.value
+        return out
 
     def set_event_log(self, keep_multipliers: bool) -> None:
         _check(lib().sail_set_event_log(self._h, int(bool(keep_multipliers))), "sail_set_event_log")

@@ -34,7 +34,8 @@ def test_binding_structs_match_the_header(S, tmp_path):
     """Every struct the binding passes by pointer has the size and field
     offsets the C compiler gives the header's declaration."""
     structs = {"sail_schedule": S.ScheduleC, "sail_job": S.JobC, "sail_job_result": S.JobResultC,
-               "sail_server_stats": S.ServerStatsC, "sail_server_config": S.ServerConfigC}
+               "sail_server_stats": S.ServerStatsC, "sail_server_config": S.ServerConfigC,
+               "sail_block_record": S.BlockRecordC}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sail.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -133,6 +134,8 @@ def test_host_side_refusals_of_the_failure_handling_entry_points(S):
     assert L.sail_server_poll(None, 1, ctypes.byref(state)) == 1
     assert L.sail_server_cancel(None, 1) == 1
     assert L.sail_read_event_margins(None, 1, None, None) == 1
+    assert L.sail_set_block_log(None, 4) == 1
+    assert L.sail_read_block_log(None, None, 0, None, None, None) == 1
 
 
 def test_no_device_reports_device_error(S):
@@ -144,3 +147,17 @@ def test_no_device_reports_device_error(S):
     with pytest.raises(S.SailError) as e:
         S.Problem(om, tau, np.exp(-tau), None, 1.0, 2.0)
     assert e.value.status == 4
+
+
+def test_allocator_hook_takes_both_functions_or_neither(S):
+    """sail_set_allocator refuses a half hook and accepts a pair or a reset;
+    no device is touched."""
+    L = S.lib()
+    assert L.sail_set_allocator(S._ALLOC_FN(lambda n, d, u: None), S._FREE_FN(), None) == 1
+    assert b"both" in L.sail_last_error()
+    assert L.sail_set_allocator(S._ALLOC_FN(), S._FREE_FN(lambda p, n, d, u: None), None) == 1
+    with pytest.raises(ValueError):
+        S.set_allocator(lambda n, d: 0, None)
+    S.set_allocator(lambda n, d: 0, lambda p, n, d: None)
+    S.set_allocator(None, None)
+    assert L.sail_set_allocator(S._ALLOC_FN(), S._FREE_FN(), None) == 0

@@ -1,0 +1,133 @@
+"""GPU: device memory from the caller's allocator (sail_set_allocator).
+
+With PyTorch's caching allocator behind the hook, the library's buffers
+count in torch's memory statistics while they live and go back to it when
+the objects are destroyed, also after the hook was changed in between.  The
+allocator does not enter the arithmetic: every result equals the run on
+hipMalloc'd memory bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_1609_07936_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1609_07936_amd import sail
+    sail.lib()
+    yield sail
+    sail.set_allocator(None, None)
+
+
+def _sched(S, wl):
+    return S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), branch_every=wl.branch_every,
+                      resync_every=wl.resync_every)
+
+
+def _problem(S, wl, prec):
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.set_tau_per_lane(16)
+    gp.init_walkers(wl.n_walkers, wl.seed, precision=prec)
+    return gp
+
+
+def _results(gp):
+    return gp.read_spectrum(), gp.read_chi2(), gp.chi2_unit
+
+
+def _solve(S, jobs, precs):
+    """One job alone, the rest as one batch; the results of each."""
+    out = []
+    gp = _problem(S, jobs[0], precs[0])
+    gp.run(_sched(S, jobs[0]), 0, jobs[0].n_sweeps)
+    out.append(_results(gp))
+    gp.close()
+    probs = [_problem(S, wl, p) for wl, p in zip(jobs[1:], precs[1:])]
+    b = S.Batch(probs)
+    b.run([_sched(S, wl) for wl in jobs[1:]], 0, [wl.n_sweeps for wl in jobs[1:]])
+    out += [_results(pr) for pr in probs]
+    b.close()
+    for pr in probs:
+        pr.close()
+    return out
+
+
+def test_torch_allocator_gives_identical_results(S):
+    import torch
+    torch.cuda.synchronize()
+    jobs = W.batch_jobs(3, base_seed=5100, n_sweeps=200)
+    precs = [S.SAIL_FP64, S.SAIL_FP32, S.SAIL_FP64]
+    ref = _solve(S, jobs, precs)
+    base = torch.cuda.memory_allocated()
+    try:
+        S.use_torch_allocator()
+        got = _solve(S, jobs, precs)
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+        # live buffers are counted by torch while the problem exists
+        wl = jobs[0]
+        gp = _problem(S, wl, S.SAIL_FP64)
+        held = torch.cuda.memory_allocated() - base
+        foot = S.footprint_bytes(wl.omega.size, wl.tau.size, wl.n_walkers, S.SAIL_FP64)
+        assert held >= foot // 2, (held, foot)
+        # a block made by the hook goes back to it after the hook is cleared
+        S.use_torch_allocator(False)
+        gp.run(_sched(S, wl), 0, wl.n_sweeps)
+        again = _results(gp)
+        gp.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+    finally:
+        S.set_allocator(None, None)
+    for (m0, c0, u0), (m1, c1, u1) in zip(ref, got):
+        np.testing.assert_array_equal(m1, m0)
+        np.testing.assert_array_equal(c1, c0)
+        assert u1 == u0
+    np.testing.assert_array_equal(again[0], ref[0][0])
+    np.testing.assert_array_equal(again[1], ref[0][1])
+
+
+def test_torch_allocator_backs_a_server_arena(S):
+    import torch
+    torch.cuda.synchronize()
+    wl = W.batch_jobs(1, base_seed=5200, n_sweeps=100)[0]
+    sc = _sched(S, wl)
+    base = torch.cuda.memory_allocated()
+    arena = 256 << 20
+    try:
+        S.use_torch_allocator()
+        srv = S.Server(hbm_bytes=arena, max_jobs=4)
+        assert torch.cuda.memory_allocated() - base >= arena
+        j = srv.submit(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1, wl.n_walkers, wl.seed, sc,
+                       precision=S.SAIL_FP32, tau_per_lane=16)
+        r = srv.wait(j, timeout=120.0)
+        srv.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+    finally:
+        S.set_allocator(None, None)
+    assert r["status"] == 0, r
+    gp = _problem(S, wl, S.SAIL_FP32)
+    gp.run(sc, 0, wl.n_sweeps)
+    np.testing.assert_array_equal(r["mean_spectrum"], gp.read_spectrum())
+    assert r["chi2_min"] == gp.read_chi2().min()
+    gp.close()
+
+
+def test_failing_allocator_reports_out_of_memory(S):
+    """An allocator that returns nothing makes problem creation fail with
+    SAIL_ENOMEM and leaves nothing behind."""
+    wl = W.batch_jobs(1, base_seed=5300, n_sweeps=10)[0]
+    try:
+        S.set_allocator(lambda n, d: 0, lambda p, n, d: None)
+        with pytest.raises(S.SailError) as e:
+            gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+            gp.init_walkers(wl.n_walkers, wl.seed)
+        assert e.value.status == 3
+    finally:
+        S.set_allocator(None, None)

@@ -681,3 +681,67 @@ def test_watchdog_detects_and_rolls_back(S):
     st = gp.read_state()
     np.testing.assert_array_equal(st["a"], planted["a"])  # NaN compares equal at the same place
     assert np.isnan(st["a"][l, j]) and np.isfinite(np.delete(st["a"].ravel(), l * wl.omega.size + j)).all()
+
+
+@pytest.mark.parametrize("case", ["max_bins", "max_lanes"])
+def test_maximum_sizes_lockstep(S, case):
+    """The largest shapes the layout takes, in lockstep with the oracle: the
+    most bins one workgroup's LDS holds (N_omega = 2556, 16 tau points) and
+    the widest lane layout, 64 lanes of 16 tau points for one walker per
+    wavefront (N_tau = 1024, the FP64 limit), each over a branching event."""
+    tgt = W.Target([1.2, 3.0], [0.3, 0.6], [0.5, 0.5], 6.0)
+    if case == "max_bins":
+        wl = W.make("mb", 6.0, 2556, W.uniform_tau(0.05, 1.5, 16), tgt, 1e-4, 13, 12, 4, 1e2, 1e-3, 2, 1, 14,
+                    n_quad=40000)
+    else:
+        wl = W.make("ml", 6.0, 48, W.uniform_tau(0.01, 4.0, 1024), tgt, 1e-4, 15, 6, 4, 1e2, 1e-3, 2, 1, 16)
+    gp, an, out = _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, dict(branch_every=2, resync_every=1))
+    lanes, tpl = gp.layout()
+    assert (lanes, tpl) == ((1, 16) if case == "max_bins" else (64, 16))
+
+
+def test_fp32_widest_layout_within_fp32_bar(S):
+    """FP32 at the largest time grid (N_tau = 1024: 32 lanes of 32 tau points,
+    two walkers per wavefront): every proposal of two sweeps against the FP64
+    oracle at 1e-5 M."""
+    import torch
+    tgt = W.Target([1.2, 3.0], [0.3, 0.6], [0.5, 0.5], 6.0)
+    wl = W.make("f32w", 6.0, 32, W.uniform_tau(0.01, 6.0, 1024), tgt, 1e-4, 17, 4, 2, 1e2, 1e-3, 100, 100, 18)
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, 100)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.set_tau_per_lane(32)
+    gp.init_walkers(4, wl.seed, precision=S.SAIL_FP32)
+    assert gp.layout() == (32, 32)
+    d, f = _trace_buffers(4, 2, wl.omega.size)
+    gp.set_trace(0, 2, d.data_ptr(), f.data_ptr())
+    gp.run(S.Schedule(T), 0, 2)
+    torch.cuda.synchronize()
+    g_d, g_f = d.cpu().numpy(), f.cpu().numpy()
+    an = O.Anneal(O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1), O.Schedule(T), 4, wl.seed)
+    out = an.run(0, 2, trace=(0, 2), replay=g_f, band=1e-5)
+    assert out["hard_mismatch"] == 0, out["first_mismatch"]
+    err = np.abs(g_d - out["dchi2"])
+    print(f"FP32 N_tau 1024: worst |dchi2 error| / M {np.max(err / out['cond']):.3e}", flush=True)
+    assert np.all(err <= 1e-5 * out["cond"])
+    np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
+
+
+def test_sizes_beyond_the_layout_are_refused(S):
+    """One tau point past the widest layout, and one walker past what the
+    branching workgroup covers, are refused with SAIL_EINVAL before any
+    sweep runs; a refused run leaves the problem usable."""
+    om = W.bin_centres(6.0, 16)
+    tau = W.uniform_tau(0.01, 6.0, 1025)
+    F = np.exp(-np.outer(tau, om)).sum(axis=1)
+    with pytest.raises(S.SailError) as e:
+        S.Problem(om, tau, F, None, 1.0, 3.0)
+    assert e.value.status == 1 and "n_tau" in str(e.value)
+    tau = W.uniform_tau(0.05, 1.5, 8)
+    F = np.exp(-np.outer(tau, om)).sum(axis=1)
+    gp = S.Problem(om, tau, F, None, 1.0, 3.0)
+    gp.init_walkers(16385, 1)
+    with pytest.raises(S.SailError) as e:
+        gp.run(S.Schedule(np.ones(10)), 0, 1)
+    assert e.value.status == 1 and "walkers" in str(e.value)
+    gp.init_walkers(16384, 1)
+    gp.run(S.Schedule(np.ones(10)), 0, 1)
