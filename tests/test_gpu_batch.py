@@ -365,3 +365,25 @@ def test_autotune_cache_file_persists_across_processes(S, tmp_path):
     assert len(valid) == 1, valid  # tuned once, appended once
     assert valid[0][1].startswith("gfx") and int(valid[0][6]) == runs[0][0] in (16, 32)
     assert runs[1][0] == runs[0][0] and runs[1][1] < 0.05, runs
+
+
+@pytest.mark.parametrize("n_walkers,prec,adaptive", [(256, 1, 0), (2048, 0, 1), (16384, 0, 0)])
+def test_parallel_branch_search_matches_the_one_workgroup_search(S, n_walkers, prec, adaptive):
+    """A single problem of 256 walkers or more searches Delta over many
+    workgroups (Sec. 2.5, the fixed bracket-and-bisect search); a batch of one
+    runs the one-workgroup search.  Ten events each: identical multipliers,
+    Delta, P_r, zero counts, status, margins and walker state."""
+    import torch
+    wl = W.small_64x32(n_sweeps=100, n_walkers=n_walkers)
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    sc = S.Schedule(T, branch_every=10, resync_every=10, adaptive=adaptive)
+    alone, one = (_problem(S, wl, prec, 16) for _ in range(2))
+    alone.run(sc, 0, wl.n_sweeps)
+    S.Batch([one]).run(sc, 0, wl.n_sweeps)
+    torch.cuda.synchronize()
+    a, b = _snapshot(alone, 10), _snapshot(one, 10)
+    _assert_same(a, b, f"{n_walkers} walkers")
+    for k in ("gap", "bracket"):
+        np.testing.assert_array_equal(a[2][k], b[2][k], err_msg=k)
+    assert np.all(a[2]["status"] == 0), a[2]["status"]
+    print(f"{n_walkers} walkers: 10 events, zero counts {a[2]['z'].tolist()}", flush=True)
