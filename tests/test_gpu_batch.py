@@ -387,3 +387,66 @@ def test_parallel_branch_search_matches_the_one_workgroup_search(S, n_walkers, p
         np.testing.assert_array_equal(a[2][k], b[2][k], err_msg=k)
     assert np.all(a[2]["status"] == 0), a[2]["status"]
     print(f"{n_walkers} walkers: 10 events, zero counts {a[2]['z'].tolist()}", flush=True)
+
+
+@pytest.mark.parametrize("eps0", [1e-7, 1e-300])
+def test_parallel_branch_search_far_bracket(S, eps0):
+    """A population whose residues span far more than the spread that sets
+    Delta: 511 walkers a few tiny moves apart and one planted two-bin
+    spectrum (both sum rules kept) with a residue ~20x theirs.  The crossing
+    Delta lies beyond d0 2^16, so the parallel search needs its second
+    bracketing round; event and state equal the one-workgroup search's bit
+    for bit, and Delta and the multipliers equal the oracle's solve on the
+    same residues and words (multipliers where the oracle finds the outcome
+    robust, Sec. 2.5 near-ties).  With a vanishing move amplitude the 511
+    residues stay equal, no Delta gives the target zero count, and both
+    searches give up after the search's 200 doublings (status 1)."""
+    import torch
+
+    import oracle as O
+    n = 512
+    wl = W.small_64x32(n_sweeps=10, n_walkers=n)
+    T = np.full(10, 1e-3)
+    sc = S.Schedule(T, branch_every=3, resync_every=1, eps0=eps0)
+    sc_nb = S.Schedule(T, branch_every=1000, resync_every=1, eps0=eps0)
+    probs = [_problem(S, wl, 0, 16) for _ in range(3)]  # alone, batch of one, twin without branching
+    blob = None
+    for gp in probs:
+        gp.run(sc, 0, 2)
+        if blob is None:
+            blob = bytearray(gp.state_export())
+            a = gp.read_state()["a"]
+            A, B = a[1].sum(), (wl.omega * a[1]).sum()
+            p, s_ = 0, wl.omega.size - 1
+            a_s = (B - wl.omega[p] * A) / (wl.omega[s_] - wl.omega[p])
+            spike = np.zeros(wl.omega.size)
+            spike[p], spike[s_] = A - a_s, a_s
+            blob[48:48 + 8 * wl.omega.size] = spike.tobytes()  # walker 0's spectrum (scale 1 after the resync)
+        gp.state_import(bytes(blob))
+    alone, one, twin = probs
+    alone.run(sc, 2, 1)
+    S.Batch([one]).run(sc, 2, 1)
+    twin.run(sc_nb, 2, 1)
+    torch.cuda.synchronize()
+    a_, b_ = _snapshot(alone, 1), _snapshot(one, 1)
+    _assert_same(a_, b_, f"far bracket eps0 {eps0}")
+    for k in ("gap", "bracket"):
+        np.testing.assert_array_equal(a_[2][k], b_[2][k], err_msg=k)
+    ev = a_[2]
+    c = twin.read_chi2()
+    d = ev["delta"][0]
+    assert c.max() > 10 * c.min()
+    if eps0 < 1e-100:
+        assert np.ptp(np.sort(c)[:-1]) == 0.0
+        assert ev["status"][0] == 1 and d == 0.0 and np.all(ev["m"][0] == 1)
+        print(f"eps0 {eps0}: status 1 (target unreachable)", flush=True)
+        return
+    print(f"eps0 {eps0}: status {ev['status'][0]}, Delta (max - min) = 2^{np.log2(d * (c.max() - c.min())):.1f}",
+          flush=True)
+    assert ev["status"][0] == 0
+    assert d * (c.max() - c.min()) > 2.0 ** 17  # beyond the first bracketing round
+    res = O.branch_solve(c, O.branch_xi(wl.seed, 0, n), 0.25)
+    assert res["status"] == 0 and not res["tie"]
+    np.testing.assert_allclose(d, res["delta"], rtol=1e-9)
+    if res["robust"]:
+        np.testing.assert_array_equal(ev["m"][0], res["m"])
