@@ -107,7 +107,10 @@ void sail_schedule_defaults(sail_schedule *s);
  *          (Sec. 2.2: A = m0 / d_omega, B = m1 / d_omega)
  *   kernel_mode  a sail_kernel_mode
  *   device HIP device ordinal the problem lives on
- * SAIL_EINFEASIBLE if m1 / m0 is not strictly inside (omega_0, omega_{n-1}). */
+ * SAIL_EINFEASIBLE if m1 / m0 is not strictly inside (omega_0, omega_{n-1}).
+ * Limits (SAIL_EINVAL beyond them): n_tau <= 1024 (64 lanes of 16 tau
+ * points per walker); n_omega as far as one workgroup's LDS holds the
+ * resync's staged spectra (n_omega <= 2556 on gfx950). */
 sail_status sail_problem_create(const double *omega, int n_omega, const double *tau, int n_tau,
                                 const double *F, const double *sigma, double m0, double m1,
                                 int kernel_mode, int device, sail_problem_t *out);
@@ -119,16 +122,19 @@ void sail_problem_destroy(sail_problem_t p);
  * a_j ~ e^{-lambda omega_j} meeting both sum rules, computes F = K a and the
  * starting residue chi^2_0 (the unit of temperature, Sec. 3).  `seed` keys
  * the Philox4x32-10 stream of every random draw.  Resets the sweep and
- * event logs. */
+ * event logs.  n_walkers >= 2, and n_walkers * n_omega doubles of spectra
+ * below 2 GiB; sail_run_schedule takes at most 16384 walkers (the
+ * branching solve's reach). */
 sail_status sail_walkers_init(sail_problem_t p, int n_walkers, uint64_t seed, int precision, void *stream);
 
 /* Runs global sweeps [first_sweep, first_sweep + n_sweeps) of `sched`.
  * A sweep is n_omega proposals per walker.  After sweep k, if (k + 1) is a
  * multiple of resync_every every walker is renormalised to both sum rules and
  * its F and chi^2 recomputed; if (k + 1) is a multiple of branch_every the
- * branching event (k + 1) / branch_every - 1 follows (Sec. 2.5).  Stages may
- * be run in several calls; the random stream depends only on the global
- * sweep, proposal and walker indices. */
+ * branching event (k + 1) / branch_every - 1 follows (Sec. 2.5; with 256
+ * walkers or more its Delta search runs over many workgroups, with the
+ * same result).  Stages may be run in several calls; the random stream
+ * depends only on the global sweep, proposal and walker indices. */
 sail_status sail_run_schedule(sail_problem_t p, const sail_schedule *sched, int first_sweep, int n_sweeps,
                               void *stream);
 
