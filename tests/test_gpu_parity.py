@@ -211,6 +211,16 @@ def test_adaptive_branching_lockstep(S, smooth):
     assert np.all(an.ev_status[:20] == 0) and z[-1] < z[0]  # fewer walkers branched as acceptance falls
 
 
+@pytest.mark.parametrize("adaptive", [0, 1])
+def test_parallel_branch_search_lockstep(S, adaptive):
+    """256 walkers, so every event runs the parallel Delta search: the small
+    workload over 10 blocks, every proposal, event and final state against
+    the oracle."""
+    wl = W.small_64x32(n_sweeps=1000, n_walkers=256)
+    gp, an, out = _anneal_lockstep(S, wl, 256, wl.seed, wl.n_sweeps, dict(adaptive=adaptive))
+    assert np.all(an.ev_status[:10] == 0)
+
+
 def test_self_cooling_lockstep(S):
     """Self-cooling (Sec. 2.4): the small workload over 20 blocks (2 boiling,
     5 cooling, 13 freezing), every proposal against the oracle, whose block
