@@ -176,6 +176,7 @@ typedef struct {
     double T;          /* absolute temperature of the block's last sweep */
     double chi2_min;   /* residues after the resync and branching */
     double chi2_mean;
+    double chi2_median; /* numpy's median: the middle residue, or the mean of the two */
     double chi2_max;
     double rate_mean;  /* running acceptance rate (Sec. 2.7), mean over walkers */
     double drift_max;  /* largest relative sum-rule drift, max(|sum a - A| / A,
@@ -184,7 +185,7 @@ typedef struct {
 } sail_block_record;
 /* capacity = 0 switches the log off.  Needs walkers (SAIL_ESTATE otherwise);
  * every call, and sail_walkers_init, empties the log.  Device memory:
- * capacity records of 56 bytes plus one double per walker.  Batches and
+ * capacity records of 64 bytes plus one double per walker.  Batches and
  * served jobs do not keep it. */
 sail_status sail_set_block_log(sail_problem_t p, int capacity);
 /* Copies the newest min(max_records, records held) records, oldest first,

@@ -67,7 +67,8 @@ class JobResultC(ctypes.Structure):
 
 class BlockRecordC(ctypes.Structure):
     _fields_ = [("sweep", ctypes.c_int32), ("event", ctypes.c_int32), ("T", ctypes.c_double),
-                ("chi2_min", ctypes.c_double), ("chi2_mean", ctypes.c_double), ("chi2_max", ctypes.c_double),
+                ("chi2_min", ctypes.c_double), ("chi2_mean", ctypes.c_double), ("chi2_median", ctypes.c_double),
+                ("chi2_max", ctypes.c_double),
                 ("rate_mean", ctypes.c_double), ("drift_max", ctypes.c_double)]
 
 

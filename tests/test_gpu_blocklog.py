@@ -33,7 +33,7 @@ def _setup(S, wl, prec, cap):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_block_log_is_the_population_statistics(S, prec):
-    wl = W.small_64x32(n_sweeps=300, n_walkers=48)
+    wl = W.small_64x32(n_sweeps=300, n_walkers=48 - prec)  # an even and an odd population (median)
     T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     every, branch = 10, 50
     gs = S.Schedule(T, branch_every=branch, resync_every=every)
@@ -43,7 +43,7 @@ def test_block_log_is_the_population_statistics(S, prec):
         gp.run(gs, k, every)
         chi2 = gp.read_chi2()
         rate = gp.read_state()["rate"]
-        ref.append((chi2.min(), chi2.mean(), chi2.max(), rate.mean()))
+        ref.append((chi2.min(), chi2.mean(), chi2.max(), rate.mean(), np.median(chi2)))
     ref = np.array(ref)
     log = gp.read_block_log()
     sweeps = np.arange(every, wl.n_sweeps + 1, every)
@@ -53,13 +53,14 @@ def test_block_log_is_the_population_statistics(S, prec):
     np.testing.assert_array_equal(log["T"], T[sweeps - 1] * gp.chi2_unit)
     np.testing.assert_array_equal(log["chi2_min"], ref[:, 0])
     np.testing.assert_array_equal(log["chi2_max"], ref[:, 2])
+    np.testing.assert_array_equal(log["chi2_median"], ref[:, 4])  # a selection: exact
     np.testing.assert_allclose(log["chi2_mean"], ref[:, 1], rtol=1e-14)
     np.testing.assert_allclose(log["rate_mean"], ref[:, 3], rtol=1e-14)
     # both sums are invariants of every move (Sec. 2.2): the drift a block
     # accumulates is rounding error
     assert np.all(log["drift_max"] >= 0) and np.all(log["drift_max"] < 1e-11), log["drift_max"]
     print(f"precision {prec}: {sweeps.size} records, largest drift {log['drift_max'].max():.2e}, "
-          f"median residue {ref[0, 1]:.3e} -> {ref[-1, 1]:.3e}", flush=True)
+          f"median residue {ref[0, 4]:.3e} -> {ref[-1, 4]:.3e}", flush=True)
 
     # the same anneal in one call gives the same records, and a ring of 4
     # keeps the newest 4 of them
@@ -69,7 +70,7 @@ def test_block_log_is_the_population_statistics(S, prec):
     ring.run(gs, 0, wl.n_sweeps)
     a, r = one.read_block_log(), ring.read_block_log()
     assert r["total"] == sweeps.size and r["sweep"].size == 4
-    for f in ("sweep", "event", "T", "chi2_min", "chi2_mean", "chi2_max", "rate_mean", "drift_max"):
+    for f in ("sweep", "event", "T", "chi2_min", "chi2_mean", "chi2_median", "chi2_max", "rate_mean", "drift_max"):
         np.testing.assert_array_equal(a[f], log[f], err_msg=f)
         np.testing.assert_array_equal(r[f], log[f][-4:], err_msg=f)
     r2 = ring.read_block_log(max_records=2)
