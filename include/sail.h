@@ -184,7 +184,9 @@ typedef struct {
                           renormalising resync before it renormalised */
 } sail_block_record;
 /* capacity = 0 switches the log off.  Needs walkers (SAIL_ESTATE otherwise);
- * every call, and sail_walkers_init, empties the log.  Device memory:
+ * every call, and sail_walkers_init, empties the log; records of blocks that
+ * a watchdog rollback undoes stay in it (their sweep numbers repeat when the
+ * run resumes).  Device memory:
  * capacity records of 64 bytes plus one double per walker.  Batches and
  * served jobs do not keep it. */
 sail_status sail_set_block_log(sail_problem_t p, int capacity);
