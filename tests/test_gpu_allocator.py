@@ -131,3 +131,59 @@ def test_failing_allocator_reports_out_of_memory(S):
         assert e.value.status == 3
     finally:
         S.set_allocator(None, None)
+
+
+def test_allocator_failing_midway_leaks_nothing(S):
+    """An allocator that runs dry after k blocks, for k across the blocks
+    walker initialisation takes: init fails with SAIL_ENOMEM, the problem
+    stays usable (a later init with hipMalloc runs), and once it is
+    destroyed every block the hook handed out has come back to it (torch's
+    count returns to where it was)."""
+    import torch
+    wl = W.batch_jobs(1, base_seed=5400, n_sweeps=20)[0]
+    live = {}
+
+    def alloc_upto(k):
+        calls = [0]
+
+        def alloc(n, d):
+            calls[0] += 1
+            if calls[0] > k:
+                return 0
+            p = torch.cuda.caching_allocator_alloc(n, device=d)
+            live[p] = n
+            return p
+        return alloc, calls
+
+    def release(p, n, d):
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    try:
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        alloc, calls = alloc_upto(10 ** 9)
+        S.set_allocator(alloc, release)
+        gp.init_walkers(wl.n_walkers, wl.seed)
+        total = calls[0]
+        assert total > 5 and len(live) == total
+        gp.close()
+        assert not live
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        for k in sorted({0, 1, total // 2, total - 1}):
+            S.set_allocator(None, None)
+            gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+            alloc, calls = alloc_upto(k)
+            S.set_allocator(alloc, release)
+            with pytest.raises(S.SailError) as e:
+                gp.init_walkers(wl.n_walkers, wl.seed)
+            assert e.value.status == 3, (k, e.value)
+            S.set_allocator(None, None)
+            gp.init_walkers(wl.n_walkers, wl.seed)  # usable after the failure
+            gp.run(S.Schedule(np.ones(10)), 0, 2)
+            gp.close()
+            assert not live, (k, len(live))  # whatever the hook handed out came back to it
+            torch.cuda.synchronize()
+            assert torch.cuda.memory_allocated() == base, k
+    finally:
+        S.set_allocator(None, None)
