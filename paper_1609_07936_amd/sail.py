@@ -240,10 +240,18 @@ def set_allocator(alloc=None, release=None) -> None:
             return None
 
     def _r(ptr, nbytes, device, _user):
-        release(int(ptr), int(nbytes), int(device))
+        try:
+            release(int(ptr), int(nbytes), int(device))
+        except Exception:  # e.g. at interpreter exit, with the allocator already torn down
+            pass
 
     pair = (_ALLOC_FN(_a), _FREE_FN(_r))
     _installed_hooks.append(pair)
+    # the library may call these for blocks it still holds while the
+    # interpreter shuts down, after this module's globals are gone: keep the
+    # two thunks alive for the life of the process
+    for cb in pair:
+        ctypes.pythonapi.Py_IncRef(ctypes.py_object(cb))
     _check(lib().sail_set_allocator(pair[0], pair[1], None), "sail_set_allocator")
 
 
