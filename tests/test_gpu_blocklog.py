@@ -97,3 +97,20 @@ def test_block_log_switches(S):
     gp.run(gs, 20, 20)  # off: nothing recorded, nothing read
     with pytest.raises(S.SailError):
         gp.read_block_log()
+
+
+def test_block_log_full_population(S):
+    """16384 walkers (the largest population): the record of each block
+    equals the statistics of the residues read back, the median exactly."""
+    wl = W.small_64x32(n_sweeps=20, n_walkers=16384)
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    gs = S.Schedule(T, branch_every=10, resync_every=10)
+    gp = _setup(S, wl, 0, 8)
+    for k in (0, 10):
+        gp.run(gs, k, 10)
+        chi2 = gp.read_chi2()
+        rec = gp.read_block_log(max_records=1)
+        assert rec["sweep"][0] == k + 10 and rec["event"][0] == k // 10
+        assert rec["chi2_min"][0] == chi2.min() and rec["chi2_max"][0] == chi2.max()
+        assert rec["chi2_median"][0] == np.median(chi2)
+        np.testing.assert_allclose(rec["chi2_mean"][0], chi2.mean(), rtol=1e-14)
