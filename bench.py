@@ -107,6 +107,32 @@ def sweep_source_digest() -> str:
     return hashlib.sha256(text[:j]).hexdigest()[:16]
 
 
+def measured_lds(workload: str, avg_launch_ms: float):
+    """LDS bytes per sweep launch (read + written) from the committed LDS
+    counter summary, with the probe's measured LDS read ceiling, if it was
+    taken on the sweep kernel's source as it stands (else None)."""
+    col = {"fp64": 0, "fp32": 1}.get(workload)
+    path = os.path.join(ROOT, "profiles", "lds_bandwidth_and_sweep_lds_counters.md")
+    if col is None or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    digest = ceiling = None
+    rows = {}
+    for line in text.splitlines():
+        if line.startswith("sweep_source_sha256_16:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("Ceiling used below:"):
+            ceiling = float(line.split(":", 1)[1].split("TB/s")[0])
+        elif line.startswith("| LDS bytes"):
+            cells = [c.strip() for c in line.strip("|").split("|")]
+            rows[cells[0]] = float(cells[1 + col])
+    if digest != sweep_source_digest() or ceiling is None or len(rows) < 2:
+        return None
+    total = rows["LDS bytes read per launch"] + rows["LDS bytes written per launch"]
+    tbs = total / (avg_launch_ms * 1e-3) / 1e12
+    return {"bytes_per_launch": total, "achieved": tbs, "ceiling": ceiling, "unit": "TB/s", "frac": tbs / ceiling}
+
+
 def measured_traffic(workload: str):
     """HBM bytes per sweep launch from the committed FETCH_SIZE / WRITE_SIZE
     summary, if it was taken on the sweep kernel's source as it stands (else
@@ -695,6 +721,7 @@ def main():
             "frac": achieved / peak,
             "traffic": measured_traffic(args.workload),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "lds": measured_lds(args.workload, avg_ms),
             "avg_launch_ms": avg_ms,
             "launches": launches,
             "sweep_share_of_step": sweep_ms / (elapsed * 1e3),

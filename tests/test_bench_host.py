@@ -39,3 +39,18 @@ def test_matched_final_chi2_and_cpu_model():
     assert bench.matched(1.04, 1.0) and bench.matched(0.96, 1.0)
     assert not bench.matched(1.06, 1.0) and not bench.matched(0.9, 1.0)
     assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+
+
+def test_lds_figures_from_the_committed_summary():
+    """roofline.lds comes from the committed LDS counter summary only while
+    its source digest matches the sweep kernel as built; its fraction is the
+    achieved LDS bandwidth over the probe's measured ceiling."""
+    import bench
+    assert bench.measured_lds("batched", 1.0) is None
+    for w, ms in (("fp64", 41.0), ("fp32", 17.0)):
+        r = bench.measured_lds(w, ms)
+        if r is None:
+            continue
+        assert r["bytes_per_launch"] > 0 and r["ceiling"] > 0
+        assert abs(r["achieved"] - r["bytes_per_launch"] / (ms * 1e-3) / 1e12) < 1e-9
+        assert abs(r["frac"] - r["achieved"] / r["ceiling"]) < 1e-12
