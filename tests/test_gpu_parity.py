@@ -1,7 +1,7 @@
 """GPU parity: the HIP library against the CPU oracle on the same seeded
 inputs and the same Philox stream.
 
-The bar (derived in the design doc from the arithmetic of the residue change):
+The bar (from the rounding of the residue change in both arithmetics):
   * |dchi2_gpu - dchi2_oracle| <= 1e-12 * M for every traced proposal, M the
     condition scale sum_i w_i (|r-1||F_i| + |dp|K_pi + |ds|K_si)(2|F_i| + 2|Ft_i| + |dF_i|);
   * identical accept decisions, except near-ties (decisions whose margin lies
