@@ -187,8 +187,9 @@ typedef struct {
  * every call, and sail_walkers_init, empties the log; records of blocks that
  * a watchdog rollback undoes stay in it (their sweep numbers repeat when the
  * run resumes).  Device memory:
- * capacity records of 64 bytes plus one double per walker.  Batches and
- * served jobs do not keep it. */
+ * capacity records of 64 bytes plus one double per walker.  A problem run
+ * in a batch keeps its log too (the same records as alone); served jobs keep
+ * none. */
 sail_status sail_set_block_log(sail_problem_t p, int capacity);
 /* Copies the newest min(max_records, records held) records, oldest first,
  * into out (host, caller-allocated) on `stream` and synchronises it;

@@ -114,3 +114,36 @@ def test_block_log_full_population(S):
         assert rec["chi2_min"][0] == chi2.min() and rec["chi2_max"][0] == chi2.max()
         assert rec["chi2_median"][0] == np.median(chi2)
         np.testing.assert_allclose(rec["chi2_mean"][0], chi2.mean(), rtol=1e-14)
+
+
+def test_block_log_in_a_batch_equals_alone(S):
+    """Problems that keep a block log and run in a batch (with a problem
+    that keeps none, and the paper's smoothing) record what they record
+    alone, bit for bit."""
+    import torch
+    jobs = W.batch_jobs(3, base_seed=6100, n_sweeps=300)
+    precs = [0, 1, 0]
+    scheds = [S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), branch_every=wl.branch_every,
+                         resync_every=wl.resync_every, smooth=0.01 * (i == 2)) for i, wl in enumerate(jobs)]
+
+    def mk(i, log):
+        wl = jobs[i]
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+        gp.init_walkers(wl.n_walkers, wl.seed, precision=precs[i])
+        if log:
+            gp.set_block_log(64)
+        return gp
+
+    alone = [mk(i, i != 1) for i in range(3)]
+    for gp, sc, wl in zip(alone, scheds, jobs):
+        gp.run(sc, 0, wl.n_sweeps)
+    mixed = [mk(i, i != 1) for i in range(3)]
+    S.Batch(mixed).run(scheds, 0, [wl.n_sweeps for wl in jobs])
+    torch.cuda.synchronize()
+    for i in (0, 2):
+        a, b = alone[i].read_block_log(), mixed[i].read_block_log()
+        assert a["total"] == b["total"] == jobs[i].n_sweeps // jobs[i].resync_every
+        for f in ("sweep", "event", "T", "chi2_min", "chi2_mean", "chi2_median", "chi2_max", "rate_mean", "drift_max"):
+            np.testing.assert_array_equal(b[f], a[f], err_msg=f"job {i} {f}")
+    with pytest.raises(S.SailError):
+        mixed[1].read_block_log()
