@@ -738,6 +738,36 @@ def test_random_shapes_lockstep(S, i):
     _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma)
 
 
+@pytest.mark.parametrize("i", range(0, 16, 2))
+def test_random_shapes_fp32_first_sweeps(S, i):
+    """The FP32 loop on the same random shapes and protocols: every proposal
+    of the first two sweeps against the FP64 oracle at the FP32 bar (1e-5 M,
+    decisions inside that band adopted by the oracle)."""
+    import torch
+    wl, kw, mode, sigma = _random_case(i)
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    sg = wl.sigma if sigma else None
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, sg, wl.m0, wl.m1, mode)
+    gp.init_walkers(wl.n_walkers, wl.seed, precision=S.SAIL_FP32)
+    print(f"case {i}: {wl.omega.size} bins, {wl.tau.size} times, {wl.n_walkers} walkers, layout {gp.layout()}",
+          flush=True)
+    ns = 2
+    d, f = _trace_buffers(wl.n_walkers, ns, wl.omega.size)
+    gp.set_trace(0, ns, d.data_ptr(), f.data_ptr())
+    gp.run(S.Schedule(T, **kw), 0, ns)
+    torch.cuda.synchronize()
+    g_d, g_f = d.cpu().numpy(), f.cpu().numpy()
+    an = O.Anneal(O.Problem(wl.omega, wl.tau, wl.Ft, sg, wl.m0, wl.m1, mode), O.Schedule(T, **kw),
+                  wl.n_walkers, wl.seed)
+    out = an.run(0, ns, trace=(0, ns), replay=g_f, band=1e-5)
+    assert out["hard_mismatch"] == 0, out["first_mismatch"]
+    err = np.abs(g_d - out["dchi2"])
+    worst = float(np.max(err / np.maximum(out["cond"], 1e-300)))
+    print(f"worst |dchi2 error| / M over {err.size} proposals: {worst:.3e}", flush=True)
+    assert np.all(err <= 1e-5 * out["cond"]), worst
+    np.testing.assert_array_equal(g_f & 1, out["accept"] & 1)
+
+
 @pytest.mark.parametrize("case", ["max_bins", "max_lanes"])
 def test_maximum_sizes_lockstep(S, case):
     """The largest shapes the layout takes, in lockstep with the oracle: the
