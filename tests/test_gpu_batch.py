@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1609_07936_amd import workloads as W
+from random_cases import random_case
 
 pytestmark = pytest.mark.gpu
 
@@ -334,6 +335,33 @@ def test_batched_jobs_against_the_oracle(S):
         alone = problem(*spec[i])
         alone.run(scheds[i], 0, k1)
         _assert_same(_snapshot(alone, k1 // 100), _snapshot(gps[i], k1 // 100), tag)
+
+
+def test_random_problems_in_one_batch_equal_alone(S):
+    """The sixteen seeded random problems and protocols (each checked against
+    the oracle alone by the parity tests), every third one with the FP32
+    loop, run together in one batch: each ends with the bits it has alone."""
+    import torch
+    cases = [random_case(i) for i in range(16)]
+    precs = [1 if i % 3 == 2 else 0 for i in range(16)]
+
+    def mk(wl, mode, sigma, prec):
+        gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma if sigma else None, wl.m0, wl.m1, mode)
+        gp.init_walkers(wl.n_walkers, wl.seed, precision=prec)
+        gp.set_event_log(True)
+        return gp
+
+    scheds = [S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), **kw) for wl, kw, _, _ in cases]
+    alone = [mk(wl, mode, sigma, p) for (wl, kw, mode, sigma), p in zip(cases, precs)]
+    for gp, sc, (wl, _, _, _) in zip(alone, scheds, cases):
+        gp.run(sc, 0, wl.n_sweeps)
+    mixed = [mk(wl, mode, sigma, p) for (wl, kw, mode, sigma), p in zip(cases, precs)]
+    S.Batch(mixed).run(scheds, 0, [wl.n_sweeps for wl, _, _, _ in cases])
+    torch.cuda.synchronize()
+    for i, (gp_a, gp_b, (wl, kw, _, _)) in enumerate(zip(alone, mixed, cases)):
+        n_ev = wl.n_sweeps // kw["branch_every"]
+        _assert_same(_snapshot(gp_a, n_ev), _snapshot(gp_b, n_ev),
+                     f"case {i} ({wl.omega.size}x{wl.tau.size}, {wl.n_walkers} walkers, prec {precs[i]})")
 
 
 def test_autotune_cache_file_persists_across_processes(S, tmp_path):
