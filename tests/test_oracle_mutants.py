@@ -1,0 +1,221 @@
+"""The oracle's pins catch plausible mistakes in it.
+
+Each case plants one mistake in a copy of the oracle: a changed constant, a
+dropped term, a flipped sign, a swapped index, operand or random word.  It
+rebuilds the copy and runs the pin suite (test_oracle_pins.py) against it,
+and the suite must fail on an assertion.  A crash does not count as caught.
+The copies live in temporary folders; the oracle itself is never touched.
+The clean copy must pass, which shows that the harness and not the copying
+is what the mutants change.
+"""
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+C = "oracle/sail_oracle.c"
+PY = "oracle/__init__.py"
+
+# (id, file, text in the oracle, planted replacement, the passage it breaks)
+MUTANTS = [
+    ("philox_multiplier", C, "(uint64_t)0xD2511F53u * (uint64_t)x0", "(uint64_t)0xD2511F55u * (uint64_t)x0",
+     "Philox4x32-10 round multiplier"),
+    ("philox_key_word", C, "uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;", "uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k1;",
+     "Philox key words"),
+    ("philox_weyl", C, "k1 += 0xBB67AE85u;", "k1 += 0x9E3779B9u;", "Philox key schedule"),
+    ("philox_rounds", C, "for (int round = 0; round < 10; ++round)", "for (int round = 0; round < 9; ++round)",
+     "Philox round count"),
+    ("u01_offset", C, "return ((double)x + 0.5) * 2.3283064365386962890625e-10;",
+     "return ((double)x + 1.0) * 2.3283064365386962890625e-10;", "word to the open unit interval"),
+    ("index_modulo", C, "return (int)(((uint64_t)x * (uint64_t)n) >> 32);", "return (int)(x % (uint32_t)n);",
+     "word to a bin index"),
+    ("point_kernel_2pi", C, "v = dw / OR_TWO_PI * exp(-omega[j] * t);", "v = dw * exp(-omega[j] * t);",
+     "Eq. correlation-model, point sampling"),
+    ("point_kernel_edge", C, "v = dw / OR_TWO_PI * exp(-omega[j] * t);",
+     "v = dw / OR_TWO_PI * exp(-(omega[j] - 0.5 * dw) * t);", "bin centres, Sec. 2.2"),
+    ("bin_exact_tau", C, "else v = (exp(-lo * t) - exp(-hi * t)) / (OR_TWO_PI * t);",
+     "else v = (exp(-lo * t) - exp(-hi * t)) / OR_TWO_PI;", "Eq. correlation-model, bin integral"),
+    ("bin_exact_edges", C, "double lo = omega[j] - 0.5 * dw, hi = omega[j] + 0.5 * dw;",
+     "double lo = omega[j], hi = omega[j] + dw;", "bin integral limits"),
+    ("forward_reversed_bins", C, "for (int j = 0; j < n_omega; ++j) s += K[(size_t)j * n_tau + i] * a[j];",
+     "for (int j = 0; j < n_omega; ++j) s += K[(size_t)j * n_tau + i] * a[n_omega - 1 - j];",
+     "Eq. correlation-model, the sum over bins"),
+    ("chi2_unweighted", C, "s += w[i] * r * r;", "s += r * r;", "Eq. residue weights"),
+    ("chi2_abs", C, "s += w[i] * r * r;", "s += w[i] * fabs(r);", "Eq. residue square"),
+    ("renorm_sign", C, "double d1 = (e1 * S0 - e0 * S1) / det;", "double d1 = (e1 * S0 + e0 * S1) / det;",
+     "two-parameter renormalisation, Sec. 2.6"),
+    ("renorm_first_only", C, "for (int j = 0; j < n; ++j) a[j] = a[j] + a[j] * (d0 + d1 * omega[j]);",
+     "for (int j = 0; j < n; ++j) a[j] = a[j] + a[j] * d0;", "renormalisation of the second sum rule"),
+    ("smooth_end", C, "a[0] = e * a[0] + s * a[1];", "a[0] = c * a[0] + s * a[1];",
+     "smoothing stencil at the ends, Sec. 2.6"),
+    ("smooth_in_place", C, "a[j] = s * prev + c * cur + s * a[j + 1];", "a[j] = s * a[j - 1] + c * cur + s * a[j + 1];",
+     "smoothing on the values before the update"),
+    ("init_mean_left_edges", C, "        s1 += e * omega[j];\n    }\n    return s1 / s0;",
+     "        s1 += e * (omega[j] - 0.5 * (omega[1] - omega[0]));\n    }\n    return s1 / s0;",
+     "max-entropy start, mean at bin centres"),
+    ("branch_threshold_sign", C, "return chi2[l] + log((double)k - xi[l]) / delta;",
+     "return chi2[l] + log((double)k + xi[l]) / delta;", "Sec. 2.5, m = floor(w + xi)"),
+    ("branch_threshold_scale", C, "return chi2[l] + log((double)k - xi[l]) / delta;",
+     "return chi2[l] + log((double)k - xi[l]) * delta;", "Sec. 2.5, weight exp(-(chi2 - P) Delta)"),
+    ("branch_zero_count_round", C, "int zt = (int)floor(fraction * (double)n + 0.5);",
+     "int zt = (int)floor(fraction * (double)n);", "Sec. 2.5, zero count round(f N)"),
+    ("branch_first_threshold", C, "or_heap_item it = {threshold(chi2, xi, l, 1, delta), l, 1};",
+     "or_heap_item it = {threshold(chi2, xi, l, 2, delta), l, 1};", "Sec. 2.5, the first copy's threshold"),
+    ("move_delta_index", C, "*dp = omr * (B - A * omega[s]) / (omega[p] - omega[s]);",
+     "*dp = omr * (B - A * omega[p]) / (omega[p] - omega[s]);", "Eq. update-delta-p"),
+    ("move_delta_sign", C, "double omr = 1.0 - r;", "double omr = r - 1.0;", "Eqs. update-delta, factor 1 - r"),
+    ("amplitude_exponent", C, "for (int c = 0; c < g->amp_m; ++c) y = y * q;",
+     "for (int c = 1; c < g->amp_m; ++c) y = y * q;", "Eq. amplitude-acceptance-adjustment, power m"),
+    ("amplitude_ratio", C, "double q = *rate / g->amp_p;", "double q = *rate;",
+     "Eq. amplitude-acceptance-adjustment, ratio to p"),
+    ("move_scale_draw", C, "double r = 1.0 - y * g->eps0 * (2.0 * ur - 1.0);", "double r = 1.0 - y * g->eps0 * ur;",
+     "Eq. update-scheme, r uniform around 1"),
+    ("positivity_one_bin", C, "int ok = (p != s) && ap >= 0.0 && as >= 0.0;", "int ok = (p != s) && ap >= 0.0;",
+     "positivity of both changed coefficients, Sec. 2.2"),
+    ("dchi2_dropped_square", C, "d += w[i] * f * (2.0 * (F[i] - Ft[i]) + f);", "d += w[i] * f * (2.0 * (F[i] - Ft[i]));",
+     "residue change, Sec. 2.2"),
+    ("dchi2_residual_sign", C, "d += w[i] * f * (2.0 * (F[i] - Ft[i]) + f);", "d += w[i] * f * (2.0 * (Ft[i] - F[i]) + f);",
+     "residue change, Sec. 2.2"),
+    ("dF_swapped_columns", C, "double f = rm1 * F[i] + dp * K[(size_t)p * Nt + i] + ds * K[(size_t)s * Nt + i];",
+     "double f = rm1 * F[i] + dp * K[(size_t)s * Nt + i] + ds * K[(size_t)p * Nt + i];",
+     "incremental F' = r F + dp K_p + ds K_s"),
+    ("dF_unscaled", C, "double f = rm1 * F[i] + dp * K[(size_t)p * Nt + i] + ds * K[(size_t)s * Nt + i];",
+     "double f = dp * K[(size_t)p * Nt + i] + ds * K[(size_t)s * Nt + i];", "incremental F', the r F term"),
+    ("metropolis_temperature", C, "int accept = ok && (d <= 0.0 || ua < exp(-d / Tabs));",
+     "int accept = ok && (d <= 0.0 || ua < exp(-d / (2.0 * Tabs)));", "Eq. probability-density"),
+    ("metropolis_uphill_only", C, "int accept = ok && (d <= 0.0 || ua < exp(-d / Tabs));",
+     "int accept = ok && (d <= 0.0);", "Eq. probability-density, uphill moves"),
+    ("accept_no_rescale", C, "for (int j = 0; j < No; ++j) a[j] = r * a[j];", "for (int j = 0; j < No; ++j) a[j] = a[j];",
+     "Eq. update-scheme-j, every coefficient scaled by r"),
+    ("rate_weights_swapped", C,
+     "*rate = (1.0 - g->amp_avg) * (*rate) + g->amp_avg * ((double)acc / (double)No);",
+     "*rate = g->amp_avg * (*rate) + (1.0 - g->amp_avg) * ((double)acc / (double)No);",
+     "running acceptance rate, Sec. 2.7"),
+    ("walk_inverted", C, "if (u01(y4[1]) * a[p] < a[pc]) p = pc;", "if (u01(y4[1]) * a[pc] < a[p]) p = pc;",
+     "Sec. 2.3, walk towards large coefficients"),
+    ("walk_word", C, "int pc = index_of(y4[0], No), sc = index_of(y4[2], No);",
+     "int pc = index_of(y4[0], No), sc = index_of(y4[0], No);", "Sec. 2.3, independent proposals for p and s"),
+    ("imprint_swapped", C, "for (int j = 0; j < No; ++j) a1[j] = t * a2[j] + (1.0 - t) * a1[j];",
+     "for (int j = 0; j < No; ++j) a1[j] = (1.0 - t) * a2[j] + t * a1[j];", "Sec. 2.5, imprint strength t"),
+    ("imprint_stale_chi2", C, "            chi2[tg[c]] = or_chi2(F + (size_t)tg[c] * Nt, g->Ft, g->w, Nt);\n", "",
+     "Sec. 2.5, the target's residue after the imprint"),
+    ("adaptive_square", C, "        fraction *= mean;\n", "        fraction *= mean * mean;\n",
+     "adaptive branching, Sec. 2.5"),
+    ("self_cool_ramp", C, "return (1.0 - x) * mean + x * mn;", "return x * mean + (1.0 - x) * mn;",
+     "self-cooling ramp, Sec. 2.4"),
+    ("self_cool_freeze", C, "return mn / (double)(1 + (b - g->boil_blocks - g->cool_blocks + 1));",
+     "return mn / (double)(1 + (b - g->boil_blocks - g->cool_blocks));", "self-cooling freeze, Sec. 2.4"),
+    ("resync_no_renorm", C, "    or_renormalize(a, g->omega, g->n_omega, g->A, g->B);\n    or_forward(", "    or_forward(",
+     "renormalisation at every resync"),
+    ("hist_bins", C, "int b = (width > 0.0) ? (int)floor((v - lo) / width * (double)n_bins) : 0;",
+     "int b = (width > 0.0) ? (int)floor((v - lo) / width * (double)(n_bins - 1)) : 0;", "residue histogram"),
+    ("mean_spectrum", C, "out[j] = s / (double)n_walkers;", "out[j] = s / (double)(n_walkers - 1);",
+     "Eq. residue-average"),
+    ("counter_words", C, "draw(g->seed, (uint32_t)q, (uint32_t)k, gl, OR_STREAM_PROPOSAL, x);",
+     "draw(g->seed, (uint32_t)k, (uint32_t)q, gl, OR_STREAM_PROPOSAL, x);", "one Philox block per (proposal, sweep, walker)"),
+    ("sweep_length", C, "for (int q = 0; q < No; ++q) {\n            uint32_t x[4];",
+     "for (int q = 0; q < No - 1; ++q) {\n            uint32_t x[4];", "a sweep is N_omega proposals, Sec. 2.2"),
+    ("commit_swapped_bins", C, "                a[p] = ap;\n                a[s] = as;\n",
+     "                a[p] = as;\n                a[s] = ap;\n", "Eqs. update-scheme-p/s"),
+    ("commit_chi2_sign", C, "*chi2 = *chi2 + d;", "*chi2 = *chi2 - d;", "residue after an accepted move"),
+    ("branch_xi_word", C, "        xi[l] = u01(x[0]);\n", "        xi[l] = u01(x[1]);\n",
+     "the branching uniforms xi, Sec. 2.5"),
+    ("rate_start", C, "        rate[l] = 1.0;\n", "        rate[l] = 0.5;\n", "running acceptance rate starts at 1"),
+    ("self_cool_boil", C, "    if (b < g->boil_blocks) return mean;", "    if (b < g->boil_blocks) return mn;",
+     "self-cooling boil at the mean residue, Sec. 2.4"),
+    ("smooth_centre", C, "const double c = 1.0 - 2.0 * s, e = 1.0 - s;", "const double c = 1.0 - s, e = 1.0 - s;",
+     "smoothing stencil weights, Sec. 2.6"),
+    ("init_tilt_direction", C, "if (tilt_mean(omega, n, mid) > mu) lo = mid; else hi = mid;",
+     "if (tilt_mean(omega, n, mid) > mu) hi = mid; else lo = mid;", "max-entropy start, the tilt search"),
+    ("bin_exact_tau0", C, "if (t == 0.0) v = dw / OR_TWO_PI;", "if (t == 0.0) v = 1.0 / OR_TWO_PI;",
+     "bin integral at tau = 0"),
+    ("resync_no_forward", C, "    or_forward(g->K, g->n_omega, g->n_tau, a, F);\n    *chi2 = or_chi2(F, g->Ft, g->w, g->n_tau);\n}",
+     "    *chi2 = or_chi2(F, g->Ft, g->w, g->n_tau);\n}", "resync recomputes F = K a"),
+    ("hist_clamp_low", C, "        if (b < 0) b = 0;\n", "        if (b < 0) b = n_bins - 1;\n",
+     "residue histogram, values below the range"),
+    ("weights_sigma", PY, "1.0 / (_f64(self.sigma) ** 2)", "1.0 / _f64(self.sigma)", "Eq. residue, w = 1/sigma^2"),
+    ("sum_rule_scale", PY, "self.A = self.m0 / dw", "self.A = self.m0", "Sec. 2.2, int S = d_omega sum a"),
+]
+
+
+def _copy_tree(dst):
+    shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(dst, "oracle"),
+                    ignore=shutil.ignore_patterns("*.so", "*.tmp", "__pycache__"))
+    os.makedirs(os.path.join(dst, "paper_1609_07936_amd"))
+    for f in ("__init__.py", "workloads.py"):
+        shutil.copy(os.path.join(ROOT, "paper_1609_07936_amd", f), os.path.join(dst, "paper_1609_07936_amd", f))
+    os.makedirs(os.path.join(dst, "tests"))
+    for f in ("conftest.py", "test_oracle_pins.py", "rocrand_philox_ref.cpp"):
+        shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(dst, "tests", f))
+
+
+def _plant(dst, path, find, repl):
+    p = os.path.join(dst, path)
+    src = open(p).read()
+    assert src.count(find) == 1, f"{path}: the planted text must occur once ({src.count(find)} found)"
+    open(p, "w").write(src.replace(find, repl))
+
+
+def _rocrand_available():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    return os.path.exists(hipcc) and os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h")
+
+
+def _env(rocrand):
+    env = dict(os.environ, OMP_NUM_THREADS="2", PYTHONDONTWRITEBYTECODE="1")
+    env.pop("SAIL_ORACLE_LIB", None)
+    if rocrand:
+        env["SAIL_ROCRAND_REF"] = rocrand
+    return env
+
+
+def _pins(dst, rocrand):
+    """Builds the copy's oracle and runs its pins; (exit code, first failure)."""
+    env = _env(rocrand)
+    subprocess.run([sys.executable, "-c", "import oracle; oracle.build()"], cwd=dst, env=env, check=True,
+                   capture_output=True, timeout=300)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                        "tests/test_oracle_pins.py"], cwd=dst, env=env, capture_output=True, text=True, timeout=600)
+    failed = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
+    return r.returncode, (failed[0] if failed else r.stdout[-300:])
+
+
+@pytest.fixture(scope="module")
+def results(tmp_path_factory):
+    base = str(tmp_path_factory.mktemp("oracle_mutants"))
+    rocrand = None
+    if _rocrand_available():
+        rocrand = os.path.join(base, "rr_ref")
+        subprocess.run([shutil.which("hipcc") or "/opt/rocm/bin/hipcc", "-O1", "-o", rocrand,
+                        os.path.join(ROOT, "tests", "rocrand_philox_ref.cpp")],
+                       check=True, cwd="/tmp", timeout=600, capture_output=True)
+    jobs = [("clean", None, None, None)] + [(m[0], m[1], m[2], m[3]) for m in MUTANTS]
+
+    def one(job):
+        name, path, find, repl = job
+        dst = os.path.join(base, name)
+        _copy_tree(dst)
+        if path:
+            _plant(dst, path, find, repl)
+        return name, _pins(dst, rocrand)
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        return dict(ex.map(one, jobs))
+
+
+def test_unmodified_copy_passes_its_pins(results):
+    code, first = results["clean"]
+    assert code == 0, first
+
+
+@pytest.mark.parametrize("mid,path,find,repl,what", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_a_planted_mistake(results, mid, path, find, repl, what):
+    if mid.startswith("philox") and not _rocrand_available():
+        pytest.skip("the Philox pin needs the independent rocRAND implementation (hipcc and its headers)")
+    code, first = results[mid]
+    print(f"{mid} ({what}): {first}")
+    assert code == 1, f"planted mistake '{mid}' ({what}) not caught by an assertion: exit {code}, {first}"

@@ -26,6 +26,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # --------------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def rocrand_ref(tmp_path_factory):
+    prebuilt = os.environ.get("SAIL_ROCRAND_REF")  # a reference already built from the same source
+    if prebuilt and os.path.exists(prebuilt):
+        return prebuilt
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
         pytest.skip("hipcc / rocRAND headers not available")
@@ -138,6 +141,29 @@ def test_forward_is_linear_and_chi2_unweighted_default():
     assert math.isclose(O.chi2(F, Ft, np.ones(5)), float(np.sum((F - Ft) ** 2)), rel_tol=1e-14)
     w = rng.uniform(1, 2, 5)
     assert math.isclose(O.chi2(F, Ft, w), float(np.sum(w * (F - Ft) ** 2)), rel_tol=1e-14)
+
+
+def test_weighted_residue_of_the_true_spectrum_is_chi_square_distributed():
+    """Eq. (residue) with errors sigma_i: for data drawn as F(a) plus
+    Gaussian noise of standard deviation sigma_i, the residue of a itself is
+    a chi-square variable with N_tau degrees of freedom (mean N_tau, variance
+    2 N_tau), whatever the scale of the sigma_i (here spread over three
+    decades)."""
+    rng = np.random.default_rng(41)
+    om = W.bin_centres(6.0, 24)
+    tau = np.linspace(0.05, 2.0, 16)
+    a = W.lorentzian(om, 2.0, 0.5) + 0.1
+    dw = om[1] - om[0]
+    F = O.forward(O.kernel_table(O.POINT, om, tau), a)
+    sigma = F * 10.0 ** rng.uniform(-5, -2, tau.size)
+    vals = []
+    for _ in range(400):
+        prob = O.Problem(om, tau, F + sigma * rng.standard_normal(tau.size), sigma, dw * a.sum(),
+                         dw * (a * om).sum())
+        vals.append(O.chi2(O.forward(prob.K, a), prob.Ft, prob.w))
+    mean, se = float(np.mean(vals)), math.sqrt(2.0 * tau.size / len(vals))
+    assert abs(mean - tau.size) < 5.0 * se, (mean, tau.size, se)
+    assert abs(np.var(vals) / (2.0 * tau.size) - 1.0) < 0.4
 
 
 # --------------------------------------------------------------------------
@@ -392,6 +418,12 @@ def test_selection_walk_distribution_is_exact_markov_power(walk_len):
         expect = pi * n
         stat = np.sum((counts - expect) ** 2 / expect)
         assert stat < 25.0, (key, counts, expect)  # chi-square, 5 dof: P(> 25) < 2e-4
+    # p and s come from independent walks (their own words of each step's
+    # block), so their joint law is the product of the two
+    joint = np.bincount(out["p"][:, 0, 0] * No + out["s"][:, 0, 0], minlength=No * No)
+    expect = np.outer(pi, pi).ravel() * n
+    stat = np.sum((joint - expect) ** 2 / expect)
+    assert stat < 80.0, stat  # chi-square, 35 dof: P(> 80) < 2e-5
     # the walk must matter: its law differs measurably from the uniform start
     assert np.max(np.abs(pi - 1.0 / No)) > 0.02
 
@@ -411,6 +443,46 @@ def test_zero_temperature_never_raises_chi2_and_infinite_accepts_all_admissible(
         else:
             assert np.array_equal(acc, ok)
             assert (~ok).sum() > 0  # the positivity cut is exercised
+
+
+def test_uphill_moves_are_taken_with_the_boltzmann_probability():
+    """Eq. (probability-density): an admissible proposal that raises the
+    residue by d is taken with probability exp(-d / T).  Over the traced
+    proposals of sweeps whose temperatures make most uphill moves neither
+    certain nor hopeless, the taken fraction in each band of exp(-d / T)
+    matches that band's mean probability (binomial standard errors), and
+    every decision equals the rule applied to the fourth word of the
+    proposal's Philox block (the reading of the uniform it draws)."""
+    wl, prob = _small_problem()
+    S, n = 40, 16
+    # temperatures spanning the residue changes of the first sweeps
+    T = np.geomspace(3e-3, 3e-5, S)
+    an = O.Anneal(prob, O.Schedule(T, branch_every=10 ** 6, resync_every=10 ** 6), n, 5)
+    out = an.run(0, S, trace=(0, S))
+    assert out["proposals"] == n * S * prob.omega.size  # a sweep is N_omega proposals per walker
+    d, acc = out["dchi2"], (out["accept"] & 1).astype(bool)
+    ok = (out["accept"] & 2).astype(bool)
+    Tabs = (T * an.chi2_unit)[None, :, None]
+    prob_take = np.where(d <= 0.0, 1.0, np.exp(-np.maximum(d, 0.0) / Tabs))
+    up = ok & (d > 0.0)
+    assert up.sum() > 5000
+    sensitive = 0
+    for lo, hi in ((0.05, 0.3), (0.3, 0.5), (0.5, 0.7), (0.7, 0.95)):
+        sel = up & (prob_take >= lo) & (prob_take < hi)
+        k = int(sel.sum())
+        sensitive += k
+        assert k > 100, (lo, hi, k)
+        pbar = float(prob_take[sel].mean())
+        frac = float(acc[sel].mean())
+        assert abs(frac - pbar) < 5.0 * math.sqrt(pbar * (1 - pbar) / k), (lo, hi, frac, pbar, k)
+    assert not np.any(acc & ~ok)
+    assert np.all(acc[ok & (d <= 0.0)])
+    # decision by decision, from the proposal's own uniform
+    key = (5 & 0xFFFFFFFF, 5 >> 32)
+    ls, ks, qs = np.nonzero(up)
+    for l, k, q in zip(ls[::7], ks[::7], qs[::7]):
+        u = O.u01(O.philox4x32_10((int(q), int(k), int(l), 0), key)[3])
+        assert bool(acc[l, k, q]) == bool(u < math.exp(-d[l, k, q] / (T[k] * an.chi2_unit)))
 
 
 # --------------------------------------------------------------------------
@@ -486,7 +558,7 @@ def test_noise_free_tiny_problem_recovers_near_zero_chi2():
 # --------------------------------------------------------------------------
 def test_branch_multipliers_follow_the_paper_formula():
     rng = np.random.default_rng(17)
-    for n in (16, 64, 257, 1000):
+    for n in (16, 19, 63, 64, 257, 259, 1000, 1003):  # 19/4, 63/4, 259/4, 1003/4 round up
         chi2 = np.exp(rng.normal(0, 1.0, n))
         xi = rng.uniform(0, 1, n)
         res = O.branch_solve(chi2, xi, 0.25)
@@ -627,6 +699,7 @@ def test_pairing_and_imprint_invariants():
             assert abs(before[l1].sum() - prob.A) <= 1e-13 * prob.A
             assert abs((before[l1] * prob.omega).sum() - prob.B) <= 1e-13 * prob.B
             np.testing.assert_allclose(an.F[l1], O.forward(prob.K, before[l1]), rtol=1e-15)
+            assert math.isclose(an.chi2[l1], O.chi2(an.F[l1], prob.Ft, prob.w), rel_tol=1e-14)
         keep = np.setdiff1d(np.arange(32), tg)
         assert np.array_equal(before[keep], pre[keep])
 
@@ -775,3 +848,6 @@ def test_outputs():
     assert h.sum() == 16 and h[0] >= 1 and h[-1] >= 1
     h2 = O.chi2_hist(np.array([1.0, 10.0, 100.0, 1000.0]), 3, 0.0, 3.0)
     assert h2.tolist() == [1, 1, 2]
+    # values outside [lo, hi) land in the end bins they lie beyond
+    h3 = O.chi2_hist(np.array([1e-3, 0.5, 10.0, 1e6]), 3, 0.0, 3.0)
+    assert h3.tolist() == [2, 1, 1]
