@@ -137,6 +137,10 @@ MUTANTS = [
      "    *chi2 = or_chi2(F, g->Ft, g->w, g->n_tau);\n}", "resync recomputes F = K a"),
     ("hist_clamp_low", C, "        if (b < 0) b = 0;\n", "        if (b < 0) b = n_bins - 1;\n",
      "residue histogram, values below the range"),
+    ("replay_adopts_everything", C, "                        if (near) {\n", "                        if (1) {\n",
+     "near-tie adoption of decisions taken elsewhere (only inside the band)"),
+    ("robust_never", C, "    int same = 1;\n    for (int pat = 0;", "    int same = 0;\n    for (int pat = 0;",
+     "branching near-ties (only events that move under a perturbation)"),
     ("weights_sigma", PY, "1.0 / (_f64(self.sigma) ** 2)", "1.0 / _f64(self.sigma)", "Eq. residue, w = 1/sigma^2"),
     ("sum_rule_scale", PY, "self.A = self.m0 / dw", "self.A = self.m0", "Sec. 2.2, int S = d_omega sum a"),
 ]

@@ -653,6 +653,41 @@ def test_branch_replay_rule():
     assert not np.array_equal(wide.a, ref.a)
 
 
+def test_accept_replay_rule():
+    """Accept decisions taken elsewhere are adopted only inside the near-tie
+    band: a planted flip of a decision far from its threshold (a downhill
+    move taken, and an uphill move refused) counts as a hard mismatch at its
+    position and leaves the oracle's own run (bit-identical to a run without
+    replay); with the band widened to cover them the same flips are adopted
+    as logged near-ties and change the run."""
+    wl, prob = _small_problem()
+    S, n = 3, 8
+    sched = O.Schedule(np.full(S, 1e-6), branch_every=10 ** 6, resync_every=10 ** 6)  # cold: uphill moves refused
+    ref = O.Anneal(prob, sched, n, 4)
+    rout = ref.run(0, S, trace=(0, S))
+    flags = rout["accept"].copy()
+    d, M = rout["dchi2"], rout["cond"]
+    acc, ok = (flags & 1).astype(bool), (flags & 2).astype(bool)
+    down = np.argwhere(acc & ok & (d < -1e-3 * M))
+    up = np.argwhere(~acc & ok & (d > 1e-3 * M) & (d > 50.0 * ref.chi2_unit * sched.T[None, :S, None]))
+    assert len(down) and len(up)
+    l1, k1, q1 = (int(v) for v in down[0])
+    l2, k2, q2 = (int(v) for v in up[-1])
+    planted = flags.copy()
+    planted[l1, k1, q1] ^= 1
+    planted[l2, k2, q2] ^= 1
+    hard = O.Anneal(prob, sched, n, 4)
+    out = hard.run(0, S, trace=(0, S), replay=planted)
+    assert out["hard_mismatch"] == 2 and out["near_ties"] == 0
+    assert out["first_mismatch"] == min((l1, k1, q1), (l2, k2, q2))
+    np.testing.assert_array_equal(hard.a, ref.a)
+    np.testing.assert_array_equal(hard.chi2, ref.chi2)
+    wide = O.Anneal(prob, sched, n, 4)
+    out = wide.run(0, S, trace=(0, S), replay=planted, band=1e3)
+    assert out["hard_mismatch"] == 0 and out["near_ties"] >= 2
+    assert not np.array_equal(wide.a, ref.a)
+
+
 def test_branch_multiplier_has_mean_w():
     """E[floor(w + xi)] = w for xi uniform on (0, 1) (Sec. 2.5)."""
     rng = np.random.default_rng(1)
