@@ -141,6 +141,11 @@ MUTANTS = [
      "near-tie adoption of decisions taken elsewhere (only inside the band)"),
     ("robust_never", C, "    int same = 1;\n    for (int pat = 0;", "    int same = 0;\n    for (int pat = 0;",
      "branching near-ties (only events that move under a perturbation)"),
+    ("cond_inflated", C, "M += w[i] * mag * (2.0 * fabs(F[i]) + 2.0 * fabs(Ft[i]) + fabs(dF[i]));",
+     "M += 1e6 * w[i] * mag * (2.0 * fabs(F[i]) + 2.0 * fabs(Ft[i]) + fabs(dF[i]));",
+     "the parity bar's condition scale (a lenient bar)"),
+    ("cond_no_residual", C, "M += w[i] * mag * (2.0 * fabs(F[i]) + 2.0 * fabs(Ft[i]) + fabs(dF[i]));",
+     "M += w[i] * mag * fabs(dF[i]);", "the parity bar's condition scale (a bar below the residue change)"),
     ("weights_sigma", PY, "1.0 / (_f64(self.sigma) ** 2)", "1.0 / _f64(self.sigma)", "Eq. residue, w = 1/sigma^2"),
     ("sum_rule_scale", PY, "self.A = self.m0 / dw", "self.A = self.m0", "Sec. 2.2, int S = d_omega sum a"),
 ]

@@ -653,6 +653,24 @@ def test_branch_replay_rule():
     assert not np.array_equal(wide.a, ref.a)
 
 
+def test_condition_scale_bounds_the_residue_change():
+    """The parity bar's scale M (every term of the residue change taken in
+    absolute value, the residual bounded through |F| + |Ft|) bounds |dchi2|
+    by the triangle inequality, and is of its natural size: from the start
+    spectrum, where the residual is of the order of the data, the median
+    M / |dchi2| of admissible proposals is of order ten (a scale inflated by
+    orders of magnitude would make the bar lenient)."""
+    wl, prob = _small_problem()
+    an = O.Anneal(prob, O.Schedule(np.full(20, 1e2), branch_every=10 ** 6, resync_every=10 ** 6), 8, 3)
+    out = an.run(0, 20, trace=(0, 20))
+    ok = (out["accept"] & 2).astype(bool)
+    d, M = np.abs(out["dchi2"][ok]), out["cond"][ok]
+    assert ok.sum() > 4000
+    assert np.all(M >= d * (1.0 - 1e-12))
+    ratio = float(np.median(M / d))
+    assert 1.0 < ratio < 100.0, ratio
+
+
 def test_accept_replay_rule():
     """Accept decisions taken elsewhere are adopted only inside the near-tie
     band: a planted flip of a decision far from its threshold (a downhill
