@@ -187,3 +187,31 @@ def test_allocator_failing_midway_leaks_nothing(S):
             assert torch.cuda.memory_allocated() == base, k
     finally:
         S.set_allocator(None, None)
+
+
+def test_failed_block_log_resize_keeps_the_old_log(S):
+    """Switching the block log to a new capacity allocates the new ring
+    before it drops the old one: when the allocation fails (SAIL_ENOMEM) the
+    old log and its records stay as they were, and the next block appends."""
+    wl = W.small_64x32(n_sweeps=40, n_walkers=16)
+    gs = S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, 40), branch_every=20, resync_every=10)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(wl.n_walkers, wl.seed)
+    gp.set_block_log(8)
+    gp.run(gs, 0, 20)
+    before = gp.read_block_log()
+    assert before["total"] == 2
+    try:
+        S.set_allocator(lambda n, d: 0, lambda p, n, d: None)
+        with pytest.raises(S.SailError) as e:
+            gp.set_block_log(64)
+        assert e.value.status == 3
+    finally:
+        S.set_allocator(None, None)
+    after = gp.read_block_log()
+    assert after["total"] == 2
+    for f in ("sweep", "T", "chi2_min", "chi2_median"):
+        np.testing.assert_array_equal(after[f], before[f])
+    gp.run(gs, 20, 10)
+    assert gp.read_block_log()["total"] == 3
+    gp.close()
