@@ -242,6 +242,9 @@ sail_status sail_read_state(sail_problem_t p, double *a, double *F, double *rate
  * be NULL. */
 sail_status sail_read_events(sail_problem_t p, int n_events, double *delta, double *pr, int32_t *z,
                              int32_t *status, int32_t *m);
+/* Keeps the multipliers of every later event (keep_multipliers = 1; each
+ * such call starts an empty multiplier log) or stops keeping them (0).
+ * Needs initialised walkers; a failed call (SAIL_ENOMEM) changes nothing. */
 sail_status sail_set_event_log(sail_problem_t p, int keep_multipliers);
 
 /* Margins of the branching solves of events [0, n_events) (Sec. 2.5), host

@@ -215,3 +215,30 @@ def test_failed_block_log_resize_keeps_the_old_log(S):
     gp.run(gs, 20, 10)
     assert gp.read_block_log()["total"] == 3
     gp.close()
+
+
+def test_failed_event_log_switch_keeps_the_old_multipliers(S):
+    """Starting a new multiplier log allocates it before dropping the old
+    one: when the allocation fails the multipliers of the events run so far
+    stay readable, and events keep being logged."""
+    wl = W.small_64x32(n_sweeps=60, n_walkers=16)
+    gs = S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, 60), branch_every=20, resync_every=10)
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(wl.n_walkers, wl.seed)
+    gp.set_event_log(True)
+    gp.run(gs, 0, 40)
+    before = gp.read_events(2, multipliers=True)
+    assert np.all(before["m"].sum(axis=1) == wl.n_walkers)
+    try:
+        S.set_allocator(lambda n, d: 0, lambda p, n, d: None)
+        with pytest.raises(S.SailError) as e:
+            gp.set_event_log(True)
+        assert e.value.status == 3
+    finally:
+        S.set_allocator(None, None)
+    np.testing.assert_array_equal(gp.read_events(2, multipliers=True)["m"], before["m"])
+    gp.run(gs, 40, 20)
+    ev = gp.read_events(3, multipliers=True)
+    np.testing.assert_array_equal(ev["m"][:2], before["m"])
+    assert ev["m"][2].sum() == wl.n_walkers
+    gp.close()
