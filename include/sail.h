@@ -18,8 +18,9 @@
  *    "device".  Input arrays are copied; the caller keeps ownership.
  *  - Output arrays are caller-allocated.
  *  - Every call returns a sail_status; nothing throws or aborts across the
- *    ABI.  On an error the call changes no state, and sail_last_error()
- *    returns a message for the calling thread.
+ *    ABI.  On an error the call changes no state (one exception:
+ *    sail_walkers_init, see there), and sail_last_error() returns a message
+ *    for the calling thread.
  *  - A problem is used from one host thread at a time.  Work is enqueued on
  *    the HIP stream passed as `stream` (NULL means the null stream); calls
  *    that return host data synchronise that stream.
@@ -124,7 +125,10 @@ void sail_problem_destroy(sail_problem_t p);
  * the Philox4x32-10 stream of every random draw.  Resets the sweep and
  * event logs.  n_walkers >= 2, and n_walkers * n_omega doubles of spectra
  * below 2 GiB; sail_run_schedule takes at most 16384 walkers (the
- * branching solve's reach). */
+ * branching solve's reach).  The previous walkers (and their logs, trace
+ * window aside) are released first, so that the new population can use
+ * their memory: after a failed call the problem holds no walkers and the
+ * calls that need them return SAIL_ESTATE until an initialisation succeeds. */
 sail_status sail_walkers_init(sail_problem_t p, int n_walkers, uint64_t seed, int precision, void *stream);
 
 /* Runs global sweeps [first_sweep, first_sweep + n_sweeps) of `sched`.

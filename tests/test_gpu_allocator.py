@@ -179,6 +179,9 @@ def test_allocator_failing_midway_leaks_nothing(S):
                 gp.init_walkers(wl.n_walkers, wl.seed)
             assert e.value.status == 3, (k, e.value)
             S.set_allocator(None, None)
+            with pytest.raises(S.SailError) as e:  # a failed initialisation leaves no walkers
+                gp.run(S.Schedule(np.ones(10)), 0, 2)
+            assert e.value.status == 6, (k, e.value)
             gp.init_walkers(wl.n_walkers, wl.seed)  # usable after the failure
             gp.run(S.Schedule(np.ones(10)), 0, 2)
             gp.close()
