@@ -1,9 +1,10 @@
 """The oracle's pins catch plausible mistakes in it.
 
-Each case plants one mistake in a copy of the oracle: a changed constant, a
-dropped term, a flipped sign, a swapped index, operand or random word.  It
-rebuilds the copy and runs the pin suite (test_oracle_pins.py) against it,
-and the suite must fail on an assertion.  A crash does not count as caught.
+Each case plants one mistake in a copy of the oracle, or of the seeded input
+generators: a changed constant, a dropped term, a flipped sign, a swapped
+index, operand or random word.  It rebuilds the copy and runs the pin suites
+(test_oracle_pins.py and test_workloads.py) against it, and the suites must
+fail on an assertion.  A crash does not count as caught.
 The copies live in temporary folders; the oracle itself is never touched.
 The clean copy must pass, which shows that the harness and not the copying
 is what the mutants change.
@@ -19,6 +20,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 C = "oracle/sail_oracle.c"
 PY = "oracle/__init__.py"
+WL = "paper_1609_07936_amd/workloads.py"  # the seeded input generators, pinned in test_workloads.py
 
 # (id, file, text in the oracle, planted replacement, the passage it breaks)
 MUTANTS = [
@@ -148,6 +150,28 @@ MUTANTS = [
      "M += w[i] * mag * fabs(dF[i]);", "the parity bar's condition scale (a bar below the residue change)"),
     ("weights_sigma", PY, "1.0 / (_f64(self.sigma) ** 2)", "1.0 / _f64(self.sigma)", "Eq. residue, w = 1/sigma^2"),
     ("sum_rule_scale", PY, "self.A = self.m0 / dw", "self.A = self.m0", "Sec. 2.2, int S = d_omega sum a"),
+    ("wl_lorentzian_width", WL, "return (gamma / np.pi) / ((w - w0) ** 2 + gamma ** 2)",
+     "return (gamma / np.pi) / ((w - w0) ** 2 + gamma)", "Lorentzian line shape, Sec. 5.2"),
+    ("wl_lorentzian_mass", WL, "- np.arctan((lo - w0) / gamma)) / np.pi)", "- np.arctan((lo - w0) / gamma)) / (2 * np.pi))",
+     "unit zeroth moment of the target"),
+    ("wl_simpson", WL, "wts[1:-1:2] = 4.0", "wts[1:-1:2] = 2.0", "Simpson weights of the transform quadrature"),
+    ("wl_transform_2pi", WL, "F = np.array([np.dot(wq, np.exp(-x * t)) for t in tau]) / TWO_PI",
+     "F = np.array([np.dot(wq, np.exp(-x * t)) for t in tau])", "Eq. transform, the 1/2pi"),
+    ("wl_first_moment", WL, "m1 = float(np.dot(wq, x))", "m1 = float(np.dot(wq, x * x))", "first moment of the target"),
+    ("wl_bin_centres", WL, "return (np.arange(n_omega, dtype=np.float64) + 0.5) * dw",
+     "return np.arange(n_omega, dtype=np.float64) * dw", "bin centres"),
+    ("wl_tau_step", WL, "dt = (t1 - t0) / (n_tau - 1)", "dt = (t1 - t0) / n_tau", "uniform time grid"),
+    ("wl_schedule_exponent", WL, "return t_hi * (t_lo / t_hi) ** (k / (n_sweeps - 1))\n\n\ndef resampled_data",
+     "return t_hi * (t_lo / t_hi) ** (k / n_sweeps)\n\n\ndef resampled_data", "geometric temperature schedule, Sec. 3"),
+    ("wl_resampled_counts", WL, "counts = (L - np.arange(n_tau)).astype(np.float64)",
+     "counts = np.full(n_tau, float(L))", "Sec. 5.1, the autocorrelation estimate averages over all origins"),
+    ("wl_resampled_sigma", WL, "sigma = np.sqrt(var / n_seq)", "sigma = np.sqrt(var)",
+     "Sec. 5.1, the error of the mean over sequences"),
+    ("wl_band_clip", WL, "tgt = Target([1.0, 2.0], [1.0, 1.0], [1.0, 1.0], 3.5, lo=0.5, hi=2.5)",
+     "tgt = Target([1.0, 2.0], [1.0, 1.0], [1.0, 1.0], 3.5, lo=0.0, hi=2.5)", "Eq. lorentzian-band, the clip"),
+    ("wl_skew", WL, "return float(abs(left - (a.sum() - left)) / a.sum())", "return float(abs(left - a.sum()) / a.sum())",
+     "Sec. 5.3, the skew"),
+    ("wl_noise_level", WL, "    sigma = noise * F\n", "    sigma = noise * np.abs(F).mean()\n", "noise sigma_i = level F_i"),
 ]
 
 
@@ -158,7 +182,7 @@ def _copy_tree(dst):
     for f in ("__init__.py", "workloads.py"):
         shutil.copy(os.path.join(ROOT, "paper_1609_07936_amd", f), os.path.join(dst, "paper_1609_07936_amd", f))
     os.makedirs(os.path.join(dst, "tests"))
-    for f in ("conftest.py", "test_oracle_pins.py", "rocrand_philox_ref.cpp"):
+    for f in ("conftest.py", "test_oracle_pins.py", "test_workloads.py", "rocrand_philox_ref.cpp"):
         shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(dst, "tests", f))
 
 
@@ -188,7 +212,7 @@ def _pins(dst, rocrand):
     subprocess.run([sys.executable, "-c", "import oracle; oracle.build()"], cwd=dst, env=env, check=True,
                    capture_output=True, timeout=300)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
-                        "tests/test_oracle_pins.py"], cwd=dst, env=env, capture_output=True, text=True, timeout=600)
+                        "tests/test_oracle_pins.py", "tests/test_workloads.py"], cwd=dst, env=env, capture_output=True, text=True, timeout=600)
     failed = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
     return r.returncode, (failed[0] if failed else r.stdout[-300:])
 
