@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--tpl", type=int, default=0,
                     help="fp64/fp32: tau points per lane (0: the library's choice; FP64 8 or 16, FP32 16 or 32)")
     ap.add_argument("--cpu-sample-walkers", type=int, default=4096)
-    ap.add_argument("--cpu-sample-sweeps", type=int, default=100)
+    ap.add_argument("--cpu-sample-sweeps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-finish", action="store_true",
                     help="fp64/fp32: skip the untimed rest of the anneal (final chi2 then stays unmeasured)")
