@@ -608,6 +608,42 @@ def test_fp32_anneal_quality_against_fp64(S):
     assert np.sum(np.abs(s32 - s64)) * dw < 0.5
 
 
+def test_fp32_anneal_within_the_oracles_seed_spread(S):
+    """Whole anneals of the small workload, statistically: the FP32 loop's
+    final median residue and averaged spectrum lie within 3x the FP64
+    oracle's own seed-to-seed spread of an ensemble of six other seeds (the
+    median within 3 standard deviations of the ensemble mean, the spectrum
+    within 3x the largest distance of an ensemble member from the ensemble
+    mean, in L1), and both sum rules hold to rounding."""
+    wl = W.small_64x32()
+    T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
+    dw = wl.omega[1] - wl.omega[0]
+    op = O.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    med, spec = [], []
+    for sd in range(wl.seed + 1000, wl.seed + 1006):
+        an = O.Anneal(op, O.Schedule(T), 64, sd)
+        an.run(0, wl.n_sweeps)
+        med.append(float(np.median(an.chi2 / an.chi2_unit)))
+        spec.append(an.mean_spectrum())
+    med, spec = np.array(med), np.array(spec)
+    centre = spec.mean(axis=0)
+    l1_members = np.array([np.sum(np.abs(s - centre)) * dw for s in spec])
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    gp.init_walkers(64, wl.seed, precision=S.SAIL_FP32)
+    gp.run(S.Schedule(T, resync_every=50), 0, wl.n_sweeps)
+    m32 = float(np.median(gp.read_chi2() / gp.chi2_unit))
+    l1_32 = float(np.sum(np.abs(gp.read_spectrum() - centre)) * dw)
+    print(f"oracle medians {np.round(med, 6)} (sd {med.std(ddof=1):.3g}); FP32 {m32:.6g}; spectrum L1 from the "
+          f"ensemble mean: members up to {l1_members.max():.3g}, FP32 {l1_32:.3g}", flush=True)
+    assert med.std(ddof=1) > 0
+    assert abs(m32 - med.mean()) <= 3.0 * med.std(ddof=1)
+    assert l1_32 <= 3.0 * l1_members.max()
+    a = gp.read_state()["a"]
+    A, B = wl.m0 / dw, wl.m1 / dw
+    assert np.max(np.abs(a.sum(axis=1) - A)) <= 1e-12 * A
+    assert np.max(np.abs((a * wl.omega).sum(axis=1) - B)) <= 1e-12 * B
+
+
 def test_checkpoint_resume_is_bit_exact(S):
     """Export after 250 sweeps, destroy, import into a fresh problem and
     continue: identical bits to the uninterrupted run (counter-based stream)."""
