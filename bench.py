@@ -533,7 +533,8 @@ def band(args):
     sched = S.Schedule(np.ones(wl.n_sweeps), branch_every=SWEEPS_PER_STEP, resync_every=SWEEPS_PER_STEP,
                        smooth=0.01, adaptive=1, self_cool=1, boil_blocks=20, cool_blocks=args.band_cool)
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
-    gp.autotune_layout(wl.n_walkers, S.SAIL_FP64, stream=stream)  # 1500 walkers fill few CUs: pick the lanes
+    # 1500 walkers fill few CUs, and the job has the device to itself: the smallest tile is a candidate
+    gp.autotune_layout(wl.n_walkers, S.SAIL_FP64, stream=stream, alone=True)
     gp.init_walkers(wl.n_walkers, wl.seed, stream=stream)
     gp.set_timing(True)
     torch.cuda.synchronize()

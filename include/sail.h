@@ -413,17 +413,21 @@ size_t sail_footprint_bytes(int n_omega, int n_tau, int n_walkers, int precision
 /* Lanes per walker and tau points per lane the sweep kernel uses. */
 sail_status sail_layout(sail_problem_t p, int *lanes_per_walker, int *tau_per_lane);
 
-/* Requests tau points per lane for the next sail_walkers_init: 8 or 16 for
- * FP64, 16 or 32 for FP32, 0 for the library's choice (16).  A
+/* Requests tau points per lane for the next sail_walkers_init: 4, 8 or 16
+ * for FP64, 8, 16 or 32 for FP32, 0 for the library's choice (16).  A
  * request the precision does not take falls back to the choice.  The walkers
- * per wavefront follow as 64 / next_pow2(ceil(n_tau / tau_per_lane)).  The
- * layout changes only the summation order of the residue change. */
+ * per wavefront follow as 64 / next_pow2(ceil(n_tau / tau_per_lane)); the
+ * smaller tiles give each walker more lanes, which pays when too few walkers
+ * fill the device.  The layout changes only the summation order of the
+ * residue change.  Any other value: SAIL_EINVAL. */
 sail_status sail_set_tau_per_lane(sail_problem_t p, int tau_per_lane);
 
 /* Chooses the tau points per lane for this problem at n_walkers walkers and
- * `precision` by timing a few sweeps of each candidate layout on `stream`,
- * and requests it as sail_set_tau_per_lane does (*tau_per_lane receives it,
- * may be NULL).  The served loop tunes each new shape after the rounds
+ * `precision` by timing a few sweeps of each candidate layout on `stream`
+ * (the two larger tiles of the precision: 8 and 16 for FP64, 16 and 32 for
+ * FP32, the right candidates when the job will share the device with
+ * others, as in a batch or the served loop), and requests it as
+ * sail_set_tau_per_lane does (*tau_per_lane receives it, may be NULL).  The served loop tunes each new shape after the rounds
  * already enqueued have drained, so the candidates run on an otherwise idle
  * device.  Results are cached per (device architecture,
  * n_omega, n_tau, n_walkers, precision) for the life of the process, and
@@ -432,6 +436,16 @@ sail_status sail_set_tau_per_lane(sail_problem_t p, int tau_per_lane);
  * line).  Leaves the problem without walkers: call it before
  * sail_walkers_init. */
 sail_status sail_autotune_layout(sail_problem_t p, int n_walkers, int precision, int *tau_per_lane, void *stream);
+
+/* As sail_autotune_layout, for a problem that will have the device to
+ * itself: the smallest tile (4 tau points per lane for FP64, 8 for FP32) is
+ * a candidate too.  More lanes per walker shorten each proposal's serial
+ * chain for more total work, which wins when the walkers alone leave the
+ * device underfilled and loses once other jobs fill it.  Its choices are
+ * cached apart from sail_autotune_layout's (a SAIL_TUNE_CACHE line tagged
+ * sail-tune-alone-v1). */
+sail_status sail_autotune_layout_alone(sail_problem_t p, int n_walkers, int precision, int *tau_per_lane,
+                                       void *stream);
 
 /* Device memory from the caller's allocator (for instance a framework's
  * caching allocator, so the library's buffers count against its pool).

@@ -155,6 +155,8 @@ def lib() -> ctypes.CDLL:
     L.sail_set_tau_per_lane.restype = st
     L.sail_autotune_layout.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_int), P]
     L.sail_autotune_layout.restype = st
+    L.sail_autotune_layout_alone.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_int), P]
+    L.sail_autotune_layout_alone.restype = st
     L.sail_batch_create.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(P)]
     L.sail_batch_create.restype = st
     L.sail_batch_destroy.argtypes = [P]
@@ -455,12 +457,15 @@ class Problem:
     def set_tau_per_lane(self, tpl: int) -> None:
         _check(lib().sail_set_tau_per_lane(self._h, int(tpl)), "sail_set_tau_per_lane")
 
-    def autotune_layout(self, n_walkers: int, precision: int = SAIL_FP64, stream=None) -> int:
+    def autotune_layout(self, n_walkers: int, precision: int = SAIL_FP64, stream=None, alone: bool = False) -> int:
         """Times the candidate lane layouts and requests the fastest for the
-        next init_walkers (this leaves the problem without walkers)."""
+        next init_walkers (this leaves the problem without walkers); alone:
+        the problem has the device to itself, so the smallest tile is a
+        candidate too."""
         v = ctypes.c_int()
-        _check(lib().sail_autotune_layout(self._h, int(n_walkers), int(precision), ctypes.byref(v),
-                                          _stream_handle(stream)), "sail_autotune_layout")
+        fn, name = ((lib().sail_autotune_layout_alone, "sail_autotune_layout_alone") if alone
+                    else (lib().sail_autotune_layout, "sail_autotune_layout"))
+        _check(fn(self._h, int(n_walkers), int(precision), ctypes.byref(v), _stream_handle(stream)), name)
         self.n_walkers = 0
         return v.value
 

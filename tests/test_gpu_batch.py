@@ -27,8 +27,8 @@ def S():
 # (label, precision, tau points per lane, first sweep, sweeps)
 MIX = [
     (0, 1, 16, 0, 200), (1, 1, 32, 50, 150), (2, 0, 16, 100, 100), (3, 0, 8, 0, 175),
-    (4, 1, 16, 25, 200), (5, 1, 32, 0, 100), (6, 0, 16, 50, 125), (7, 1, 16, 150, 50),
-    (8, 0, 8, 75, 125), (9, 1, 32, 0, 200),
+    (4, 1, 16, 25, 200), (5, 1, 32, 0, 100), (6, 0, 16, 50, 125), (7, 1, 8, 150, 50),
+    (8, 0, 4, 75, 125), (9, 1, 32, 0, 200),
 ]
 
 
@@ -163,6 +163,24 @@ def test_autotune_layout(S):
         t0 = time.perf_counter()
         assert gp.autotune_layout(wl.n_walkers, prec) == tpl
         assert time.perf_counter() - t0 < 0.05
+
+
+def test_autotune_layout_alone_adds_the_smallest_tile(S):
+    """For a problem with the device to itself the autotuner also times the
+    smallest tile; its choice is cached apart from the shared one, so a
+    shared call for the same shape still picks one of the two larger tiles."""
+    import time
+    wl = W.batch_jobs(1, base_seed=5151, n_sweeps=100)[0]
+    gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
+    for prec, small, shared in ((S.SAIL_FP32, 8, (16, 32)), (S.SAIL_FP64, 4, (8, 16))):
+        tpl = gp.autotune_layout(wl.n_walkers, prec, alone=True)
+        assert tpl in (small,) + shared
+        gp.init_walkers(wl.n_walkers, wl.seed, precision=prec)
+        assert gp.layout()[1] == tpl
+        t0 = time.perf_counter()
+        assert gp.autotune_layout(wl.n_walkers, prec, alone=True) == tpl
+        assert time.perf_counter() - t0 < 0.05
+        assert gp.autotune_layout(wl.n_walkers, prec) in shared
 
 
 def test_batch_protocol_bit_identical_to_alone(S):

@@ -32,12 +32,13 @@ def S():
     return sail
 
 
-def _pair(S, wl, n_walkers, seed, sched_kw=None, mode=0, sigma=True, T=None):
+def _pair(S, wl, n_walkers, seed, sched_kw=None, mode=0, sigma=True, T=None, tpl=0):
     sched_kw = sched_kw or {}
     if T is None:
         T = W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps)
     sg = wl.sigma if sigma else None
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, sg, wl.m0, wl.m1, mode)
+    gp.set_tau_per_lane(tpl)
     gp.init_walkers(n_walkers, seed)
     op = O.Problem(wl.omega, wl.tau, wl.Ft, sg, wl.m0, wl.m1, mode)
     return gp, S.Schedule(T, **sched_kw), op, O.Schedule(T, **sched_kw)
@@ -94,9 +95,9 @@ def _same_or_near_tie(m_gpu, res, tag=""):
     return m_gpu
 
 
-def _anneal_lockstep(S, wl, n_walkers, seed, n_sweeps, sched_kw=None, mode=0, sigma=True, T=None):
+def _anneal_lockstep(S, wl, n_walkers, seed, n_sweeps, sched_kw=None, mode=0, sigma=True, T=None, tpl=0):
     import torch
-    gp, gs, op, osch = _pair(S, wl, n_walkers, seed, sched_kw, mode, sigma, T)
+    gp, gs, op, osch = _pair(S, wl, n_walkers, seed, sched_kw, mode, sigma, T, tpl)
     an = O.Anneal(op, osch, n_walkers, seed)
     assert abs(gp.chi2_unit / an.chi2_unit - 1) < 1e-12
     gp.set_event_log(True)
@@ -119,15 +120,16 @@ def _anneal_lockstep(S, wl, n_walkers, seed, n_sweeps, sched_kw=None, mode=0, si
     spec = gp.read_spectrum()
     dw = wl.omega[1] - wl.omega[0]
     assert np.sum(np.abs(spec - an.mean_spectrum())) * dw <= 1e-10 * wl.m0
-    _assert_untraced_twin(S, wl, n_walkers, seed, n_sweeps, gs, mode, sigma, gp, n_ev)
+    _assert_untraced_twin(S, wl, n_walkers, seed, n_sweeps, gs, mode, sigma, gp, n_ev, tpl=tpl)
     return gp, an, out
 
 
-def _assert_untraced_twin(S, wl, n_walkers, seed, n_sweeps, gs, mode, sigma, gp, n_ev, precision=0):
+def _assert_untraced_twin(S, wl, n_walkers, seed, n_sweeps, gs, mode, sigma, gp, n_ev, precision=0, tpl=0):
     """The same run without a trace window takes the kernel variant the
     benchmark times; its state, residues and branching log equal the traced
     (oracle-checked) run bit for bit."""
     tw = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma if sigma else None, wl.m0, wl.m1, mode)
+    tw.set_tau_per_lane(tpl)
     tw.init_walkers(n_walkers, seed, precision=precision)
     tw.set_event_log(True)
     tw.run(gs, 0, n_sweeps)
@@ -557,10 +559,10 @@ def test_errors_leave_problem_usable(S):
     assert np.all(np.isfinite(gp.read_chi2()))
 
 
-@pytest.mark.parametrize("tau_per_lane", [16, 32])
+@pytest.mark.parametrize("tau_per_lane", [8, 16, 32])
 def test_fp32_loop_first_sweeps_within_fp32_bar(S, tau_per_lane):
     """FP32 residual loop (the variant the large FP32 workload runs): every proposal of the first two
-    sweeps against the FP64 oracle, in both FP32 lane layouts.  The loop
+    sweeps against the FP64 oracle, in every FP32 lane layout.  The loop
     carries Phi and the columns in FP32, so the bar is
     (TPL + log2 L + 8) u_32 M <= 1e-5 M; decisions whose margin falls inside
     that band are adopted by the oracle."""
@@ -738,6 +740,19 @@ def test_random_shapes_lockstep(S, i):
     print(f"case {i}: {wl.omega.size} bins, {wl.tau.size} times, {wl.n_walkers} walkers, {wl.n_sweeps} sweeps, "
           f"mode {mode}, weighted {sigma}, {kw}", flush=True)
     _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma)
+
+
+@pytest.mark.parametrize("i,tpl", [(1, 4), (4, 8), (7, 4), (10, 8), (13, 4)])
+def test_random_shapes_lockstep_small_tiles(S, i, tpl):
+    """The smaller FP64 tiles (4 and 8 tau points per lane: more lanes per
+    walker, a longer reduction) on random shapes and protocols, in lockstep
+    with the oracle over every branching event, as at the default tile."""
+    wl, kw, mode, sigma = _random_case(i)
+    print(f"case {i}, {tpl} tau per lane: {wl.omega.size} bins, {wl.tau.size} times, {wl.n_walkers} walkers, "
+          f"{wl.n_sweeps} sweeps, mode {mode}, weighted {sigma}, {kw}", flush=True)
+    gp, _, _ = _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma, tpl=tpl)
+    lanes, got = gp.layout()
+    assert got == tpl or (got > tpl and lanes == 64), (lanes, got)
 
 
 @pytest.mark.parametrize("i", range(0, 16, 2))
