@@ -172,9 +172,9 @@ def test_autotune_layout_alone_adds_the_smallest_tile(S):
     import time
     wl = W.batch_jobs(1, base_seed=5151, n_sweeps=100)[0]
     gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)
-    for prec, small, shared in ((S.SAIL_FP32, 8, (16, 32)), (S.SAIL_FP64, 4, (8, 16))):
+    for prec, small, shared in ((S.SAIL_FP32, (8,), (16, 32)), (S.SAIL_FP64, (4,), (8, 16))):
         tpl = gp.autotune_layout(wl.n_walkers, prec, alone=True)
-        assert tpl in (small,) + shared
+        assert tpl in small + shared
         gp.init_walkers(wl.n_walkers, wl.seed, precision=prec)
         assert gp.layout()[1] == tpl
         t0 = time.perf_counter()
@@ -358,22 +358,28 @@ def test_batched_jobs_against_the_oracle(S):
 def test_random_problems_in_one_batch_equal_alone(S):
     """The sixteen seeded random problems and protocols (each checked against
     the oracle alone by the parity tests), every third one with the FP32
-    loop, run together in one batch: each ends with the bits it has alone."""
+    loop, the tile requests cycling through every tile of the precision and
+    the library's choice, run together in one batch: each ends with the
+    bits it has alone."""
     import torch
     cases = [random_case(i) for i in range(16)]
     precs = [1 if i % 3 == 2 else 0 for i in range(16)]
+    tiles = [((4, 8, 16, 0) if precs[i] == 0 else (8, 16, 32, 0))[i % 4] for i in range(16)]
 
-    def mk(wl, mode, sigma, prec):
+    def mk(wl, mode, sigma, prec, tpl):
         gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma if sigma else None, wl.m0, wl.m1, mode)
+        gp.set_tau_per_lane(tpl)
         gp.init_walkers(wl.n_walkers, wl.seed, precision=prec)
         gp.set_event_log(True)
         return gp
 
     scheds = [S.Schedule(W.geometric_schedule(wl.t_hi, wl.t_lo, wl.n_sweeps), **kw) for wl, kw, _, _ in cases]
-    alone = [mk(wl, mode, sigma, p) for (wl, kw, mode, sigma), p in zip(cases, precs)]
+    alone = [mk(wl, mode, sigma, p, t) for (wl, kw, mode, sigma), p, t in zip(cases, precs, tiles)]
+    used = {(p, gp.layout()[1]) for p, gp in zip(precs, alone)}
+    assert {(0, 4), (0, 8), (0, 16), (1, 8), (1, 16), (1, 32)} <= used, used
     for gp, sc, (wl, _, _, _) in zip(alone, scheds, cases):
         gp.run(sc, 0, wl.n_sweeps)
-    mixed = [mk(wl, mode, sigma, p) for (wl, kw, mode, sigma), p in zip(cases, precs)]
+    mixed = [mk(wl, mode, sigma, p, t) for (wl, kw, mode, sigma), p, t in zip(cases, precs, tiles)]
     S.Batch(mixed).run(scheds, 0, [wl.n_sweeps for wl, _, _, _ in cases])
     torch.cuda.synchronize()
     for i, (gp_a, gp_b, (wl, kw, _, _)) in enumerate(zip(alone, mixed, cases)):

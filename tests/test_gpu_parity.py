@@ -742,11 +742,12 @@ def test_random_shapes_lockstep(S, i):
     _anneal_lockstep(S, wl, wl.n_walkers, wl.seed, wl.n_sweeps, kw, mode, sigma)
 
 
-@pytest.mark.parametrize("i,tpl", [(1, 4), (4, 8), (7, 4), (10, 8), (13, 4)])
+@pytest.mark.parametrize("i,tpl", [(0, 4), (3, 4), (5, 4), (6, 4), (8, 8), (12, 4), (14, 4), (15, 8), (3, 8)])
 def test_random_shapes_lockstep_small_tiles(S, i, tpl):
     """The smaller FP64 tiles (4 and 8 tau points per lane: more lanes per
-    walker, a longer reduction) on random shapes and protocols, in lockstep
-    with the oracle over every branching event, as at the default tile."""
+    walker, a longer reduction) on random shapes and protocols spanning 2 to
+    64 lanes, in lockstep with the oracle over every branching event, as at
+    the default tile."""
     wl, kw, mode, sigma = _random_case(i)
     print(f"case {i}, {tpl} tau per lane: {wl.omega.size} bins, {wl.tau.size} times, {wl.n_walkers} walkers, "
           f"{wl.n_sweeps} sweeps, mode {mode}, weighted {sigma}, {kw}", flush=True)
