@@ -391,7 +391,8 @@ def test_random_problems_in_one_batch_equal_alone(S):
 def test_autotune_cache_file_persists_across_processes(S, tmp_path):
     """With SAIL_TUNE_CACHE naming a file, a layout tuned in one process is
     appended to it as one line and a second process takes it from the file
-    without timing anything (malformed lines are ignored)."""
+    without timing anything (malformed lines are ignored); the choice for a
+    problem with the device to itself is a line of its own tag."""
     import os
     import subprocess
     import sys
@@ -404,19 +405,21 @@ def test_autotune_cache_file_persists_across_processes(S, tmp_path):
             "wl = W.batch_jobs(1, base_seed=4242, n_sweeps=100)[0]\n"
             "gp = S.Problem(wl.omega, wl.tau, wl.Ft, wl.sigma, wl.m0, wl.m1)\n"
             "t0 = time.perf_counter(); tpl = gp.autotune_layout(wl.n_walkers, S.SAIL_FP32)\n"
-            "print(tpl, time.perf_counter() - t0, flush=True)\n") % root
+            "t1 = time.perf_counter(); tpa = gp.autotune_layout(wl.n_walkers, S.SAIL_FP32, alone=True)\n"
+            "print(tpl, t1 - t0, tpa, time.perf_counter() - t1, flush=True)\n") % root
     env = dict(os.environ, SAIL_TUNE_CACHE=str(cache))
     runs = []
     for _ in range(2):
         r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=180)
         assert r.returncode == 0, r.stderr[-2000:]
-        tpl, dt = r.stdout.split()
-        runs.append((int(tpl), float(dt)))
-    lines = [ln.split() for ln in cache.read_text().splitlines() if ln.startswith("sail-tune-v1")]
-    valid = [ln for ln in lines if len(ln) == 7]
-    assert len(valid) == 1, valid  # tuned once, appended once
-    assert valid[0][1].startswith("gfx") and int(valid[0][6]) == runs[0][0] in (16, 32)
-    assert runs[1][0] == runs[0][0] and runs[1][1] < 0.05, runs
+        tpl, dt, tpa, dta = r.stdout.split()
+        runs.append((int(tpl), float(dt), int(tpa), float(dta)))
+    text = cache.read_text().splitlines()
+    for tag, col, cands in (("sail-tune-v1", 0, (16, 32)), ("sail-tune-alone-v1", 2, (8, 16, 32))):
+        valid = [ln.split() for ln in text if ln.split()[:1] == [tag] and len(ln.split()) == 7]
+        assert len(valid) == 1, (tag, valid)  # tuned once, appended once
+        assert valid[0][1].startswith("gfx") and int(valid[0][6]) == runs[0][col] in cands
+        assert runs[1][col] == runs[0][col] and runs[1][col + 1] < 0.05, runs
 
 
 @pytest.mark.parametrize("n_walkers,prec,adaptive", [(256, 1, 0), (2048, 0, 1), (16384, 0, 0)])
